@@ -1,0 +1,226 @@
+"""ctypes binding of libcpgrad (include/cpgrad.h): argument marshalling only.
+
+Every call takes torch tensors that live on the GPU, checks their type,
+shape and contiguity, and passes raw device pointers to the C ABI.  No step
+of the computation runs here; if the shared library is missing the import of
+this module raises, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libcpgrad.so")
+
+CPG_F64, CPG_F32, CPG_BF16 = 0, 1, 2
+CPG_MODE_NATIVE, CPG_MODE_BF16, CPG_MODE_BF16_REFINED = 0, 1, 2
+CPG_OPT_FORCE_NSTAR, CPG_OPT_KERNEL = 1, 2
+MAX_MODES, MAX_RANK = 16, 64
+
+STATUS = {0: "CPG_OK", -1: "CPG_ERR_INVALID", -2: "CPG_ERR_NOMEM", -3: "CPG_ERR_HIP", -4: "CPG_ERR_NOT_SPD",
+          -5: "CPG_ERR_UNSUPPORTED", -6: "CPG_ERR_NONFINITE"}
+
+DTYPES = {"f64": CPG_F64, "f32": CPG_F32, "bf16": CPG_BF16}
+MODES = {"native": CPG_MODE_NATIVE, "bf16": CPG_MODE_BF16, "bf16_refined": CPG_MODE_BF16_REFINED}
+TORCH_DTYPE = {CPG_F64: torch.float64, CPG_F32: torch.float32, CPG_BF16: torch.bfloat16}
+
+EXPORTS = ["cpgrad_plan", "cpgrad_plan_info", "cpgrad_query", "cpgrad_set_option", "cpgrad_bind", "cpgrad_all_modes",
+           "cpals_step", "cp_fit", "cpgrad_last_fit", "cpgrad_destroy", "cpgrad_status_string",
+           "cpgrad_version"]
+
+
+class CpgError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__(f"{where}: {STATUS.get(status, status)} ({status})")
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1204_1586_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64p = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "cpgrad_plan": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.c_int, i64p, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_int, ctypes.c_int, vp]),
+        "cpgrad_plan_info": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_size_t),
+                                            dp, dp]),
+        "cpgrad_query": (ctypes.c_int, [ctypes.c_int, i64p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_int), dp, dp]),
+        "cpgrad_set_option": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int64]),
+        "cpgrad_bind": (ctypes.c_int, [vp, vp]),
+        "cpgrad_all_modes": (ctypes.c_int, [vp, vp, ctypes.POINTER(vp), ctypes.POINTER(vp)]),
+        "cpals_step": (ctypes.c_int, [vp, vp, ctypes.POINTER(vp), dp, dp]),
+        "cp_fit": (ctypes.c_int, [vp, vp, ctypes.POINTER(vp), dp, dp]),
+        "cpgrad_last_fit": (ctypes.c_int, [vp, dp, dp]),
+        "cpgrad_destroy": (ctypes.c_int, [vp]),
+        "cpgrad_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+        "cpgrad_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+LIB = _load()
+
+
+def _check(status, where):
+    if status != 0:
+        raise CpgError(status, where)
+
+
+def _ptrs(ts):
+    arr = (ctypes.c_void_p * len(ts))()
+    for i, t in enumerate(ts):
+        arr[i] = t.data_ptr()
+    return arr
+
+
+class Plan:
+    """Owns a cpgrad_plan_t; the library's plan lives until destroy()/GC."""
+
+    def __init__(self, handle, dims, R, ydt, fdt, mode, stream):
+        self.handle = handle
+        self.dims = tuple(dims)
+        self.R = R
+        self.ydt, self.fdt, self.mode = ydt, fdt, mode
+        self.stream = stream
+        self.bound = None
+
+    @property
+    def N(self):
+        return len(self.dims)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            LIB.cpgrad_destroy(h)
+            self.handle = None
+
+
+def _check_y(plan, Y):
+    if not (isinstance(Y, torch.Tensor) and Y.is_cuda and Y.is_contiguous()):
+        raise ValueError("Y must be a contiguous CUDA tensor")
+    if Y.dtype != TORCH_DTYPE[plan.ydt]:
+        raise ValueError(f"Y dtype {Y.dtype} does not match the plan ({TORCH_DTYPE[plan.ydt]})")
+    n = 1
+    for d in plan.dims:
+        n *= d
+    if Y.numel() != n:
+        raise ValueError(f"Y has {Y.numel()} entries, the plan expects {n}")
+
+
+def _check_factors(plan, A, what="A"):
+    if len(A) != plan.N:
+        raise ValueError(f"{what} must hold {plan.N} tensors")
+    for n, M in enumerate(A):
+        if not (isinstance(M, torch.Tensor) and M.is_cuda and M.is_contiguous()):
+            raise ValueError(f"{what}[{n}] must be a contiguous CUDA tensor")
+        if tuple(M.shape) != (plan.dims[n], plan.R) or M.dtype != TORCH_DTYPE[plan.fdt]:
+            raise ValueError(f"{what}[{n}] must be ({plan.dims[n]}, {plan.R}) {TORCH_DTYPE[plan.fdt]}")
+
+
+def cpgrad_plan(dims, R, y_dtype="f32", factor_dtype=None, mode="native", stream=None):
+    """Create a plan (see cpgrad_plan in include/cpgrad.h).  dims[0] = I_1 is the
+    fastest mode; ``stream`` defaults to torch's current stream."""
+    ydt = DTYPES[y_dtype] if isinstance(y_dtype, str) else int(y_dtype)
+    if factor_dtype is None:
+        factor_dtype = "f64" if ydt == CPG_F64 else "f32"
+    fdt = DTYPES[factor_dtype] if isinstance(factor_dtype, str) else int(factor_dtype)
+    md = MODES[mode] if isinstance(mode, str) else int(mode)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    dims = [int(d) for d in dims]
+    arr = (ctypes.c_int64 * len(dims))(*dims)
+    h = ctypes.c_void_p()
+    _check(LIB.cpgrad_plan(ctypes.byref(h), len(dims), arr, int(R), ydt, fdt, md,
+                           ctypes.c_void_p(stream.cuda_stream)), "cpgrad_plan")
+    return Plan(h, dims, int(R), ydt, fdt, md, stream)
+
+
+def cpgrad_plan_info(plan):
+    """Returns dict(n_star, workspace_bytes, alg_flops, alg_bytes)."""
+    ns, ws = ctypes.c_int(), ctypes.c_size_t()
+    fl, by = ctypes.c_double(), ctypes.c_double()
+    _check(LIB.cpgrad_plan_info(plan.handle, ctypes.byref(ns), ctypes.byref(ws), ctypes.byref(fl),
+                                ctypes.byref(by)), "cpgrad_plan_info")
+    return {"n_star": ns.value, "workspace_bytes": ws.value, "alg_flops": fl.value, "alg_bytes": by.value}
+
+
+def cpgrad_query(dims, R, y_dtype="f32", factor_dtype=None, force_nstar=0):
+    """Host-only: dict(n_star, alg_flops, alg_bytes) for a shape (no device needed)."""
+    ydt = DTYPES[y_dtype] if isinstance(y_dtype, str) else int(y_dtype)
+    if factor_dtype is None:
+        factor_dtype = "f64" if ydt == CPG_F64 else "f32"
+    fdt = DTYPES[factor_dtype] if isinstance(factor_dtype, str) else int(factor_dtype)
+    dims = [int(d) for d in dims]
+    arr = (ctypes.c_int64 * max(1, len(dims)))(*dims)
+    ns, fl, by = ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
+    _check(LIB.cpgrad_query(len(dims), arr, int(R), ydt, fdt, int(force_nstar), ctypes.byref(ns), ctypes.byref(fl),
+                            ctypes.byref(by)), "cpgrad_query")
+    return {"n_star": ns.value, "alg_flops": fl.value, "alg_bytes": by.value}
+
+
+def cpgrad_set_option(plan, option, value):
+    _check(LIB.cpgrad_set_option(plan.handle, int(option), int(value)), "cpgrad_set_option")
+
+
+def cpgrad_bind(plan, Y):
+    _check_y(plan, Y)
+    _check(LIB.cpgrad_bind(plan.handle, ctypes.c_void_p(Y.data_ptr())), "cpgrad_bind")
+    plan.bound = Y
+
+
+def cpgrad_all_modes(plan, Y, A, G):
+    """G[n] <- Y_(n) (⊙_{k≠n} A^(k)) for all n (asynchronous)."""
+    _check_y(plan, Y)
+    _check_factors(plan, A)
+    _check_factors(plan, G, "G")
+    _check(LIB.cpgrad_all_modes(plan.handle, ctypes.c_void_p(Y.data_ptr()), _ptrs(A), _ptrs(G)),
+           "cpgrad_all_modes")
+
+
+def cpals_step(plan, Y, A, sync=True):
+    """One CP_ALS sweep, A updated in place.  Returns (cost, fit) if sync, else None."""
+    _check_y(plan, Y)
+    _check_factors(plan, A)
+    if sync:
+        c, f = ctypes.c_double(), ctypes.c_double()
+        _check(LIB.cpals_step(plan.handle, ctypes.c_void_p(Y.data_ptr()), _ptrs(A), ctypes.byref(c),
+                              ctypes.byref(f)), "cpals_step")
+        return c.value, f.value
+    _check(LIB.cpals_step(plan.handle, ctypes.c_void_p(Y.data_ptr()), _ptrs(A), None, None), "cpals_step")
+    return None
+
+
+def cp_fit(plan, Y, A):
+    """(cost, fit) of [[A]] against the bound Y."""
+    _check_y(plan, Y)
+    _check_factors(plan, A)
+    c, f = ctypes.c_double(), ctypes.c_double()
+    _check(LIB.cp_fit(plan.handle, ctypes.c_void_p(Y.data_ptr()), _ptrs(A), ctypes.byref(c), ctypes.byref(f)),
+           "cp_fit")
+    return c.value, f.value
+
+
+def cpgrad_last_fit(plan):
+    c, f = ctypes.c_double(), ctypes.c_double()
+    _check(LIB.cpgrad_last_fit(plan.handle, ctypes.byref(c), ctypes.byref(f)), "cpgrad_last_fit")
+    return c.value, f.value
+
+
+def cpgrad_destroy(plan):
+    if plan.handle:
+        _check(LIB.cpgrad_destroy(plan.handle), "cpgrad_destroy")
+        plan.handle = None
+
+
+def cpgrad_version():
+    return LIB.cpgrad_version().decode()

@@ -1,0 +1,420 @@
+// Small kernels of Algorithm 2 and of the ALS sweep (Section 4):
+//  * fixed-order float64 reduction of the split partial contractions;
+//  * the peel-off chain steps of eqs. 3.20 / 3.22 (one mode product);
+//  * the per-mode gradient of cp_gradient 'right' / 'left' (eqs. 3.12, 3.16);
+//  * float64 Gram matrices, the Cholesky solve of eq. 2.14, ||Y||^2, and the
+//    cost of eq. 2.12 with fit = 1 - ||Y - Yhat|| / ||Y||.
+// All reductions run in a fixed order, so results are bitwise reproducible.
+#include "cpg_internal.h"
+
+namespace cpg {
+
+template <typename TC>
+__device__ __forceinline__ double kr_entry_d(const FacSet<TC>& fs, int first, int count, int64_t idx, int r) {
+    double v = 1.0;
+    for (int m = 0; m < count; ++m) {
+        const int64_t d = fs.dims[first + m];
+        const int64_t q = idx / d;
+        const int64_t i = idx - q * d;
+        idx = q;
+        v *= (double)fs.A[first + m][i * fs.R + r];
+    }
+    return v;
+}
+
+__device__ __forceinline__ double block_sum_256(double v, double* sbuf) {
+    // sbuf: >= 256 doubles; returns the total in every thread
+    const int tid = threadIdx.x;
+    sbuf[tid] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) sbuf[tid] += sbuf[tid + s];
+        __syncthreads();
+    }
+    const double t = sbuf[0];
+    __syncthreads();
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// partial reduction
+// ---------------------------------------------------------------------------
+template <typename TC>
+__global__ __launch_bounds__(256) void k_reduce_parts(const TC* __restrict__ parts, int64_t nparts, int64_t n,
+                                                      TC* __restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n) return;
+    double acc = 0.0;
+    for (int64_t p = 0; p < nparts; ++p) acc += (double)parts[p * n + e];
+    out[e] = (TC)acc;
+}
+
+hipError_t launch_reduce_parts(int fdt, const void* parts, int64_t nparts, int64_t rows, int R, void* out,
+                               hipStream_t s) {
+    const int64_t n = rows * R;
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    if (fdt == CPG_F64)
+        hipLaunchKernelGGL(k_reduce_parts<double>, dim3(nb), dim3(256), 0, s, (const double*)parts, nparts, n,
+                           (double*)out);
+    else
+        hipLaunchKernelGGL(k_reduce_parts<float>, dim3(nb), dim3(256), 0, s, (const float*)parts, nparts, n,
+                           (float*)out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// one chain step: out[lo + lo_n*hi][r] = sum_i in[lo + lo_n*(i + I*hi)][r] a[i][r]
+//   right chain (eq. 3.20): lo_n = J_n, I = I_{n+1}, hi_n = 1
+//   left chain  (eq. 3.22): lo_n = 1,   I = I_{n-1}, hi_n = K_{n-1}
+// ---------------------------------------------------------------------------
+template <typename TC>
+__global__ __launch_bounds__(256) void k_ttv(const TC* __restrict__ in, TC* __restrict__ out,
+                                             const TC* __restrict__ a, int64_t lo_n, int64_t I, int64_t hi_n,
+                                             int R) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= lo_n * hi_n * R) return;
+    const int64_t row = e / R;
+    const int r = (int)(e - row * R);
+    const int64_t hi = row / lo_n;
+    const int64_t lo = row - hi * lo_n;
+    double acc = 0.0;
+    for (int64_t i = 0; i < I; ++i) acc += (double)in[(lo + lo_n * (i + I * hi)) * R + r] * (double)a[i * R + r];
+    out[e] = (TC)acc;
+}
+
+hipError_t launch_ttv(int fdt, const void* in, void* out, const void* a, int64_t lo_n, int64_t I, int64_t hi_n,
+                      int R, hipStream_t s) {
+    const int64_t n = lo_n * hi_n * R;
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    if (fdt == CPG_F64)
+        hipLaunchKernelGGL(k_ttv<double>, dim3(nb), dim3(256), 0, s, (const double*)in, (double*)out,
+                           (const double*)a, lo_n, I, hi_n, R);
+    else
+        hipLaunchKernelGGL(k_ttv<float>, dim3(nb), dim3(256), 0, s, (const float*)in, (float*)out,
+                           (const float*)a, lo_n, I, hi_n, R);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// gradient of one mode from a chain tensor (cp_gradient 'right' / 'left'):
+// G(i, r) = sum_{lo, hi} Z[lo + lo_n*(i + I*hi)][r] * KR_lo(lo, r) * KR_hi(hi, r)
+// one block per row i; threads split (r, term) and reduce in LDS.
+// ---------------------------------------------------------------------------
+template <typename TC>
+__global__ __launch_bounds__(256) void k_grad(const TC* __restrict__ Z, TC* __restrict__ G, FacSet<TC> fs,
+                                              int64_t lo_n, int64_t I, int64_t hi_n, int lo_first, int lo_count,
+                                              int hi_first, int hi_count) {
+    __shared__ double sred[256];
+    const int R = fs.R;
+    const int tid = threadIdx.x;
+    const int64_t i = blockIdx.x;
+    const int groups = 256 / R;
+    const int r = tid % R;
+    const int g = tid / R;
+    double acc = 0.0;
+    if (g < groups) {
+        const int64_t nterms = lo_n * hi_n;
+        for (int64_t t = g; t < nterms; t += groups) {
+            const int64_t hi = t / lo_n;
+            const int64_t lo = t - hi * lo_n;
+            const double z = (double)Z[(lo + lo_n * (i + I * hi)) * R + r];
+            acc += z * kr_entry_d(fs, lo_first, lo_count, lo, r) * kr_entry_d(fs, hi_first, hi_count, hi, r);
+        }
+    }
+    sred[tid] = (g < groups) ? acc : 0.0;
+    __syncthreads();
+    if (tid < R) {
+        double v = 0.0;
+        for (int q = 0; q < groups; ++q) v += sred[q * R + tid];
+        G[i * R + tid] = (TC)v;
+    }
+}
+
+hipError_t launch_grad(int fdt, const void* Z, void* G, const void* facset, int64_t lo_n, int64_t I,
+                       int64_t hi_n, int lo_first, int lo_count, int hi_first, int hi_count, hipStream_t s) {
+    if (fdt == CPG_F64)
+        hipLaunchKernelGGL(k_grad<double>, dim3((unsigned)I), dim3(256), 0, s, (const double*)Z, (double*)G,
+                           *(const FacSet<double>*)facset, lo_n, I, hi_n, lo_first, lo_count, hi_first, hi_count);
+    else
+        hipLaunchKernelGGL(k_grad<float>, dim3((unsigned)I), dim3(256), 0, s, (const float*)Z, (float*)G,
+                           *(const FacSet<float>*)facset, lo_n, I, hi_n, lo_first, lo_count, hi_first, hi_count);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// float64 Gram matrices: grams[n][r][s] = sum_i A^(n)(i,r) A^(n)(i,s)
+// ---------------------------------------------------------------------------
+template <typename TC>
+__global__ __launch_bounds__(256) void k_grams(FacSet<TC> fs, double* __restrict__ grams) {
+    const int n = blockIdx.x;
+    const int R = fs.R;
+    const TC* A = fs.A[n];
+    const int64_t I = fs.dims[n];
+    for (int e = threadIdx.x; e < R * R; e += 256) {
+        const int r = e / R, c = e - (e / R) * R;
+        double acc = 0.0;
+        for (int64_t i = 0; i < I; ++i) acc += (double)A[i * R + r] * (double)A[i * R + c];
+        grams[(int64_t)n * R * R + e] = acc;
+    }
+}
+
+hipError_t launch_grams(int fdt, const void* facset, double* grams, hipStream_t s) {
+    if (fdt == CPG_F64) {
+        const FacSet<double>& fs = *(const FacSet<double>*)facset;
+        hipLaunchKernelGGL(k_grams<double>, dim3(fs.N), dim3(256), 0, s, fs, grams);
+    } else {
+        const FacSet<float>& fs = *(const FacSet<float>*)facset;
+        hipLaunchKernelGGL(k_grams<float>, dim3(fs.N), dim3(256), 0, s, fs, grams);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// eq. 2.14 for one mode, one block:
+//   Gamma = Hadamard product of the other modes' Grams (float64),
+//   Gamma = L L^T (Cholesky; one retry with Gamma + 1e-12 tr(Gamma)/R I),
+//   each row x of A^(n) solves x Gamma = g (forward then back substitution),
+//   then grams[n] <- A^(n)^T A^(n) from the stored (rounded) factor.
+// On failure flags[0] |= 1 and A^(n), grams[n] are left untouched.
+// ---------------------------------------------------------------------------
+template <typename TC, int RT>
+__global__ __launch_bounds__(256) void k_als_update(const TC* __restrict__ G, TC* __restrict__ A,
+                                                    double* __restrict__ grams, int N, int n, int64_t I, int R,
+                                                    int* __restrict__ flags) {
+    __shared__ double sGam[RT * RT];
+    __shared__ double sL[RT * (RT + 1)];
+    __shared__ int sOk;
+    __shared__ double sTr;
+    const int tid = threadIdx.x;
+    const int LD = RT + 1;
+
+    for (int e = tid; e < R * R; e += 256) {
+        double v = 1.0;
+        for (int k = 0; k < N; ++k)
+            if (k != n) v *= grams[(int64_t)k * R * R + e];
+        sGam[e] = v;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double tr = 0.0;
+        for (int c = 0; c < R; ++c) tr += sGam[c * R + c];
+        sTr = tr;
+    }
+    __syncthreads();
+
+    bool ok = false;
+    for (int attempt = 0; attempt < 2 && !ok; ++attempt) {
+        const double jit = attempt == 0 ? 0.0 : 1e-12 * sTr / R;
+        for (int e = tid; e < R * R; e += 256) {
+            const int r = e / R, c = e - (e / R) * R;
+            sL[r * LD + c] = sGam[e] + (r == c ? jit : 0.0);
+        }
+        if (tid == 0) sOk = 1;
+        __syncthreads();
+        // left-looking column Cholesky: L[c][c], then L[i][c] for i > c
+        for (int c = 0; c < R; ++c) {
+            if (tid == 0) {
+                double d = sL[c * LD + c];
+                for (int k = 0; k < c; ++k) d -= sL[c * LD + k] * sL[c * LD + k];
+                if (!(d > 0.0) || !isfinite(d)) {
+                    sOk = 0;
+                    d = 1.0;
+                }
+                sL[c * LD + c] = sqrt(d);
+            }
+            __syncthreads();
+            const double lcc = sL[c * LD + c];
+            for (int i = c + 1 + tid; i < R; i += 256) {
+                double v = sL[i * LD + c];
+                for (int k = 0; k < c; ++k) v -= sL[i * LD + k] * sL[c * LD + k];
+                sL[i * LD + c] = v / lcc;
+            }
+            __syncthreads();
+        }
+        ok = sOk != 0;
+        __syncthreads();
+    }
+    if (!ok) {
+        if (tid == 0) atomicOr(flags, 1);
+        return;
+    }
+
+    // solve every row: z L^T = g  ->  L z^T = g^T (forward), then L^T x^T = z^T (back)
+    for (int64_t i = tid; i < I; i += 256) {
+        double x[RT];
+#pragma unroll
+        for (int c = 0; c < RT; ++c) x[c] = (c < R) ? (double)G[i * R + c] : 0.0;
+#pragma unroll
+        for (int c = 0; c < RT; ++c) {
+            if (c < R) {
+                double v = x[c];
+#pragma unroll
+                for (int k = 0; k < RT; ++k)
+                    if (k < c) v -= sL[c * LD + k] * x[k];
+                x[c] = v / sL[c * LD + c];
+            }
+        }
+#pragma unroll
+        for (int c = RT - 1; c >= 0; --c) {
+            if (c < R) {
+                double v = x[c];
+#pragma unroll
+                for (int k = 0; k < RT; ++k)
+                    if (k > c && k < R) v -= sL[k * LD + c] * x[k];
+                x[c] = v / sL[c * LD + c];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < RT; ++c)
+            if (c < R) A[i * R + c] = (TC)x[c];
+    }
+    __syncthreads();
+    for (int e = tid; e < R * R; e += 256) {
+        const int r = e / R, c = e - (e / R) * R;
+        double acc = 0.0;
+        for (int64_t i = 0; i < I; ++i) acc += (double)A[i * R + r] * (double)A[i * R + c];
+        grams[(int64_t)n * R * R + e] = acc;
+    }
+}
+
+template <typename TC>
+static hipError_t als_dispatch(const TC* G, TC* A, double* grams, int N, int n, int64_t I, int R, int* flags,
+                               hipStream_t s) {
+    if (R <= 4)
+        hipLaunchKernelGGL((k_als_update<TC, 4>), dim3(1), dim3(256), 0, s, G, A, grams, N, n, I, R, flags);
+    else if (R <= 16)
+        hipLaunchKernelGGL((k_als_update<TC, 16>), dim3(1), dim3(256), 0, s, G, A, grams, N, n, I, R, flags);
+    else if (R <= 32)
+        hipLaunchKernelGGL((k_als_update<TC, 32>), dim3(1), dim3(256), 0, s, G, A, grams, N, n, I, R, flags);
+    else
+        hipLaunchKernelGGL((k_als_update<TC, 64>), dim3(1), dim3(256), 0, s, G, A, grams, N, n, I, R, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_als_update(int fdt, const void* G, void* A, double* grams, int N, int n, int64_t I, int R,
+                             int* flags, hipStream_t s) {
+    if (fdt == CPG_F64) return als_dispatch<double>((const double*)G, (double*)A, grams, N, n, I, R, flags, s);
+    return als_dispatch<float>((const float*)G, (float*)A, grams, N, n, I, R, flags, s);
+}
+
+// ---------------------------------------------------------------------------
+// ||Y||^2 in float64 (two stages, fixed order)
+// ---------------------------------------------------------------------------
+constexpr int kRedBlocks = 1024;
+
+template <typename TY>
+__device__ __forceinline__ double yval(const TY* p, int64_t e) { return (double)p[e]; }
+template <>
+__device__ __forceinline__ double yval<uint16_t>(const uint16_t* p, int64_t e) {
+    return (double)__uint_as_float(((uint32_t)p[e]) << 16);
+}
+
+template <typename TY>
+__global__ __launch_bounds__(256) void k_norm2_stage1(const TY* __restrict__ Y, int64_t n,
+                                                      double* __restrict__ scratch) {
+    __shared__ double sbuf[256];
+    double acc = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+        const double v = yval(Y, e);
+        acc += v * v;
+    }
+    const double t = block_sum_256(acc, sbuf);
+    if (threadIdx.x == 0) scratch[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(256) void k_sum_stage2(const double* __restrict__ scratch, int nparts,
+                                                    double* __restrict__ out) {
+    __shared__ double sbuf[256];
+    double acc = 0.0;
+    for (int p = threadIdx.x; p < nparts; p += 256) acc += scratch[p];
+    const double t = block_sum_256(acc, sbuf);
+    if (threadIdx.x == 0) *out = t;
+}
+
+hipError_t launch_norm2(int ydt, const void* Y, int64_t n, double* scratch, double* out, hipStream_t s) {
+    if (ydt == CPG_F64)
+        hipLaunchKernelGGL(k_norm2_stage1<double>, dim3(kRedBlocks), dim3(256), 0, s, (const double*)Y, n, scratch);
+    else if (ydt == CPG_F32)
+        hipLaunchKernelGGL(k_norm2_stage1<float>, dim3(kRedBlocks), dim3(256), 0, s, (const float*)Y, n, scratch);
+    else
+        hipLaunchKernelGGL(k_norm2_stage1<uint16_t>, dim3(kRedBlocks), dim3(256), 0, s, (const uint16_t*)Y, n,
+                           scratch);
+    hipLaunchKernelGGL(k_sum_stage2, dim3(1), dim3(256), 0, s, scratch, kRedBlocks, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// <Y, Yhat> = sum_{j, r} P_R(j, r) * (A^(n*) (.) ... (.) A^(1))(j, r)
+// ---------------------------------------------------------------------------
+template <typename TC>
+__global__ __launch_bounds__(256) void k_inner_kr_stage1(const TC* __restrict__ PR, int64_t J, FacSet<TC> fs,
+                                                         int nstar, double* __restrict__ scratch) {
+    __shared__ double sbuf[256];
+    const int R = fs.R;
+    const int64_t n = J * R;
+    double acc = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+        const int64_t j = e / R;
+        const int r = (int)(e - j * R);
+        acc += (double)PR[e] * kr_entry_d(fs, 0, nstar, j, r);
+    }
+    const double t = block_sum_256(acc, sbuf);
+    if (threadIdx.x == 0) scratch[blockIdx.x] = t;
+}
+
+hipError_t launch_inner_kr(int fdt, const void* PR, int64_t J, const void* facset, int nstar, double* scratch,
+                           double* out, hipStream_t s) {
+    if (fdt == CPG_F64)
+        hipLaunchKernelGGL(k_inner_kr_stage1<double>, dim3(kRedBlocks), dim3(256), 0, s, (const double*)PR, J,
+                           *(const FacSet<double>*)facset, nstar, scratch);
+    else
+        hipLaunchKernelGGL(k_inner_kr_stage1<float>, dim3(kRedBlocks), dim3(256), 0, s, (const float*)PR, J,
+                           *(const FacSet<float>*)facset, nstar, scratch);
+    hipLaunchKernelGGL(k_sum_stage2, dim3(1), dim3(256), 0, s, scratch, kRedBlocks, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// cost (eq. 2.12) = ||Y||^2 - 2 <Y,Yhat> + ||Yhat||^2, fit = 1 - sqrt(cost)/||Y||
+// ---------------------------------------------------------------------------
+template <typename TC>
+__global__ __launch_bounds__(256) void k_cost_fit(const TC* __restrict__ G, const TC* __restrict__ A, int64_t I,
+                                                  int R, const double* __restrict__ inner_in,
+                                                  const double* __restrict__ grams, int N, double* __restrict__ scal,
+                                                  int* __restrict__ flags) {
+    __shared__ double sbuf[256];
+    double acc = 0.0;
+    if (G != nullptr)
+        for (int64_t e = threadIdx.x; e < I * R; e += 256) acc += (double)G[e] * (double)A[e];
+    const double inner = (G != nullptr) ? block_sum_256(acc, sbuf) : *inner_in;
+    double h = 0.0;
+    for (int e = threadIdx.x; e < R * R; e += 256) {
+        double v = 1.0;
+        for (int k = 0; k < N; ++k) v *= grams[(int64_t)k * R * R + e];
+        h += v;
+    }
+    const double nrm = block_sum_256(h, sbuf);
+    if (threadIdx.x == 0) {
+        const double y2 = scal[0];
+        const double D = y2 - 2.0 * inner + nrm;
+        const double fit = 1.0 - sqrt(D > 0.0 ? D : 0.0) / sqrt(y2);
+        scal[2] = D;
+        scal[3] = fit;
+        scal[4] = inner;
+        scal[5] = nrm;
+        if (!isfinite(D) || !isfinite(fit)) atomicOr(flags, 2);
+    }
+}
+
+hipError_t launch_cost_fit(int fdt, const void* G, const void* A, int64_t I, int R, const double* inner_in,
+                           const double* grams, int N, double* scal, int* flags, hipStream_t s) {
+    if (fdt == CPG_F64)
+        hipLaunchKernelGGL(k_cost_fit<double>, dim3(1), dim3(256), 0, s, (const double*)G, (const double*)A, I, R,
+                           inner_in, grams, N, scal, flags);
+    else
+        hipLaunchKernelGGL(k_cost_fit<float>, dim3(1), dim3(256), 0, s, (const float*)G, (const float*)A, I, R,
+                           inner_in, grams, N, scal, flags);
+    return hipGetLastError();
+}
+
+}  // namespace cpg

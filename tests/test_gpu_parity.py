@@ -1,0 +1,181 @@
+"""GPU parity: the HIP path (through the C ABI) against the float64 oracle on
+identical seeded inputs.  Tolerances (relative Frobenius error per mode):
+1e-12 for float64, 1e-5 for float32; bf16-stored tensors are compared with
+the oracle run on the exact stored values."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from gpu_util import (exact_factors, exact_tensor, factor_storage, problem, rel_fro, to_device_factors,
+                      to_device_y)
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 1e-5}
+
+
+def _all_modes(dims, R, storage, mode="native", force_nstar=0, kernel=0, seed=0):
+    import paper_1204_1586_amd as P
+    pr = problem(dims, R, storage, seed=seed)
+    fst = factor_storage(storage)
+    Y = to_device_y(pr["y"], storage)
+    A = to_device_factors(pr["init"], fst)
+    G = [torch.empty_like(M) for M in A]
+    plan = P.cpgrad_plan(dims, R, storage, fst, mode)
+    if force_nstar:
+        P.cpgrad_set_option(plan, P.CPG_OPT_FORCE_NSTAR, force_nstar)
+    if kernel:
+        P.cpgrad_set_option(plan, P.CPG_OPT_KERNEL, kernel)
+    P.cpgrad_all_modes(plan, Y, A, G)
+    torch.cuda.synchronize()
+    return pr, A, [g.cpu().double().numpy() for g in G], plan
+
+
+CASES = [
+    ((20, 20, 20), 3, "f64"),
+    ((70, 33, 45), 3, "f64"),
+    ((16, 20, 24), 64, "f64"),
+    ((20, 30, 40, 50), 16, "f32"),
+    ((5, 6, 3, 4, 2, 3, 5), 10, "f32"),
+    ((100, 77), 5, "f32"),
+    ((33, 1, 65, 7), 1, "f32"),
+    ((9, 70, 130), 33, "f32"),
+    ((12, 10, 8, 6, 4), 32, "bf16"),
+]
+
+
+@pytest.mark.parametrize("dims,R,storage", CASES)
+def test_all_modes_matches_oracle(dims, R, storage):
+    print(f"[all_modes] dims={dims} R={R} storage={storage}", flush=True)
+    mode = "native" if storage != "bf16" else "bf16_refined"
+    pr, A, G, _ = _all_modes(dims, R, storage, mode)
+    Y = exact_tensor(pr["y"], storage, dims)
+    ref = O.cp_gradient_all(Y, exact_factors(A))
+    for n in range(len(dims)):
+        assert rel_fro(G[n], ref[n]) <= TOL[storage], (n, rel_fro(G[n], ref[n]))
+
+
+def test_full_size_64_4_f32():
+    dims, R = (64, 64, 64, 64), 16
+    print(f"[all_modes full] dims={dims} R={R}", flush=True)
+    pr, A, G, plan = _all_modes(dims, R, "f32")
+    Y = exact_tensor(pr["y"], "f32", dims)
+    ref = O.cp_gradient_all(Y, exact_factors(A))
+    for n in range(4):
+        assert rel_fro(G[n], ref[n]) <= 1e-5, (n, rel_fro(G[n], ref[n]))
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_any_split_gives_the_same_gradients(storage):
+    """eqs. 3.7 = 3.8: every split point n* in [1, N-1] reaches the same G^(n)."""
+    dims, R = (6, 5, 4, 3, 2), 4
+    print(f"[force n*] storage={storage}", flush=True)
+    outs = []
+    for ns in range(1, 5):
+        pr, A, G, _ = _all_modes(dims, R, storage, force_nstar=ns)
+        outs.append(G)
+    Y = exact_tensor(pr["y"], storage, dims)
+    ref = O.cp_gradient_all(Y, exact_factors(A))
+    for G in outs:
+        for n in range(5):
+            assert rel_fro(G[n], ref[n]) <= TOL[storage]
+
+
+def test_deterministic():
+    dims, R = (20, 30, 40, 50), 16
+    _, _, G1, _ = _all_modes(dims, R, "f32")
+    _, _, G2, _ = _all_modes(dims, R, "f32")
+    for a, b in zip(G1, G2):
+        assert np.array_equal(a, b)
+
+
+# ---------------------------------------------------------------------------
+# ALS sweep (eq. 2.14, Section 4 order) and cost (eq. 2.12)
+# ---------------------------------------------------------------------------
+
+def _als_setup(dims, R, storage, mode="native", seed=0, snr=25.0):
+    import paper_1204_1586_amd as P
+    pr = problem(dims, R, storage, seed=seed, snr=snr)
+    fst = factor_storage(storage)
+    Y = to_device_y(pr["y"], storage)
+    A = to_device_factors(pr["init"], fst)
+    plan = P.cpgrad_plan(dims, R, storage, fst, mode)
+    P.cpgrad_bind(plan, Y)
+    return P, pr, Y, A, plan
+
+
+@pytest.mark.parametrize("dims,R,storage,ftol", [((20, 20, 20), 3, "f64", 1e-10), ((11, 13, 9, 7), 5, "f64", 1e-10),
+                                                 ((20, 30, 40, 50), 16, "f32", 2e-4),
+                                                 ((5, 6, 3, 4, 2, 3, 5), 10, "f32", 2e-4)])
+def test_als_sweep_matches_oracle(dims, R, storage, ftol):
+    print(f"[als] dims={dims} R={R} storage={storage}", flush=True)
+    P, pr, Y, A, plan = _als_setup(dims, R, storage)
+    A0 = exact_factors(A)
+    cost, fit = P.cpals_step(plan, Y, A)
+    Yx = exact_tensor(pr["y"], storage, dims)
+    A_ref, D_ref, fit_ref = O.als_sweep(Yx, A0)
+    A_gpu = exact_factors(A)
+    for n in range(len(dims)):
+        assert rel_fro(A_gpu[n], A_ref[n]) <= ftol, (n, rel_fro(A_gpu[n], A_ref[n]))
+    ctol = 1e-10 if storage == "f64" else 1e-4
+    assert abs(cost - D_ref) <= ctol * O.norm2(Yx)
+    assert abs(fit - fit_ref) <= (1e-10 if storage == "f64" else 1e-4)
+    # the device's cost is the explicit residual of the model it returned
+    assert abs(cost - O.cost_explicit(Yx, A_gpu)) <= ctol * O.norm2(Yx)
+
+
+def test_als_50_sweeps_3d_f64():
+    """3-D 20^3, rank 3, float64, 30 dB: 50 sweeps track the oracle's fits."""
+    import cpgen
+    import paper_1204_1586_amd as P
+    pr = cpgen.make_problem("cp3d_20_r3_f64", rep=0)
+    Y = to_device_y(pr["y"], "f64")
+    A = to_device_factors(pr["init"], "f64")
+    plan = P.cpgrad_plan(pr["dims"], pr["R"], "f64", "f64")
+    P.cpgrad_bind(plan, Y)
+    fits = [P.cpals_step(plan, Y, A)[1] for _ in range(50)]
+    _, fits_ref = O.cp_als(exact_tensor(pr["y"], "f64", pr["dims"]), pr["init"], 50)
+    assert np.max(np.abs(np.array(fits) - np.array(fits_ref))) <= 1e-10
+    assert fits[-1] > 0.9
+
+
+@pytest.mark.parametrize("dims,R,storage", [((20, 20, 20), 3, "f64"), ((20, 30, 40, 50), 16, "f32"),
+                                            ((5, 6, 3, 4, 2, 3, 5), 10, "f32")])
+def test_cp_fit_matches_explicit_residual(dims, R, storage):
+    P, pr, Y, A, plan = _als_setup(dims, R, storage)
+    cost, fit = P.cp_fit(plan, Y, A)
+    Yx = exact_tensor(pr["y"], storage, dims)
+    D = O.cost_explicit(Yx, exact_factors(A))
+    tol = 1e-11 if storage == "f64" else 1e-5
+    assert abs(cost - D) <= tol * O.norm2(Yx)
+    assert abs(fit - O.fit_from_cost(D, O.norm2(Yx))) <= tol * 10
+
+
+def test_not_spd_is_reported_and_factor_kept():
+    P, pr, Y, A, plan = _als_setup((8, 9, 10), 3, "f64")
+    for M in A:
+        M.zero_()
+    before = exact_factors(A)
+    with pytest.raises(P.CpgError) as ei:
+        P.cpals_step(plan, Y, A)
+    assert ei.value.status == -4
+    after = exact_factors(A)
+    for a, b in zip(before, after):
+        assert np.array_equal(a, b)
+
+
+def test_nonfinite_cost_is_reported():
+    P, pr, Y, A, plan = _als_setup((8, 9, 10), 3, "f32")
+    Y[5] = float("nan")
+    P.cpgrad_bind(plan, Y)
+    with pytest.raises(P.CpgError) as ei:
+        P.cp_fit(plan, Y, A)
+    assert ei.value.status in (-6, -4)
+
+
+def test_unbound_tensor_is_rejected():
+    P, pr, Y, A, plan = _als_setup((8, 9, 10), 3, "f32")
+    Y2 = Y.clone()
+    with pytest.raises(P.CpgError):
+        P.cpals_step(plan, Y2, A)
