@@ -1,0 +1,186 @@
+"""Benchmark of the fast all-mode CP gradient and the fast CP_ALS sweep on one GPU.
+
+One step = one all-mode gradient (Algorithm 2: the fused contraction pass
+over Y plus both peel-off chains) followed by one CP_ALS sweep (Section 4:
+two passes over Y, the per-mode Cholesky updates of eq. 2.14 and the float64
+cost of eq. 2.12), on the 4-D 64x64x64x64 float32 tensor of rank 16 with
+20 dB noise (synthetic, seeded).  Inputs are resident in HBM before timing.
+
+Prints one JSON line: value = all-mode CP-gradient GFLOP/s (algorithmic
+flops of Algorithm 2 / time of the all-mode call), plus ALS sweeps per second,
+the roofline of the dominant kernel (the fused contraction, timed with HIP
+events on its stream) and the oracle timed on the host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "all-mode CP-gradient GFLOP/s & ALS iters/s, plain FP32 vs BF16-refined at 1e-6 fit"
+WORKLOAD = "cp4d_64_r16_f32"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default=WORKLOAD)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget-s", type=float, default=20.0)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="only run a plain device copy of known size (for HBM counter calibration)")
+    return ap.parse_args()
+
+
+def cpu_baseline(pr, budget_s):
+    """The oracle as it stands (float64 NumPy, Algorithm 1 per mode) on the same
+    tensor: whole all-mode gradients, repeated while the budget lasts."""
+    import numpy as np
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:  # noqa: BLE001
+        cores = os.cpu_count()
+    Y = O.as_tensor(pr["y"].astype(np.float64), pr["dims"])
+    A = [np.asarray(M, dtype=np.float64) for M in pr["init"]]
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        O.cp_gradient_all(Y, A)
+        reps += 1
+        if time.perf_counter() - t0 > budget_s * 0.5 or reps >= 5:
+            break
+    dt = (time.perf_counter() - t0) / reps
+    return dt, reps, cores
+
+
+def calib_copy():
+    import torch
+    n = 64 * 1024 * 1024 // 4
+    a = torch.ones(n, device="cuda", dtype=torch.float32)
+    b = torch.empty_like(a)
+    for _ in range(20):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calib_copy_bytes_read": a.numel() * 4, "calib_copy_bytes_written": b.numel() * 4,
+                      "launches": 20}))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(the slab split of Y over GPUs is described in DESIGN.md, not built).", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    if args.calib_copy:
+        calib_copy()
+        return
+
+    import cpgen
+    import paper_1204_1586_amd as P
+
+    w = cpgen.WORKLOADS[args.workload]
+    pr = cpgen.make_problem(w, rep=0)
+    dims, R = pr["dims"], pr["R"]
+    fst = "f64" if pr["storage"] == "f64" else "f32"
+    tdt = torch.float64 if fst == "f64" else torch.float32
+    if pr["storage"] == "bf16":
+        Y = torch.from_numpy(pr["y"].view(np.int16)).view(torch.bfloat16).cuda()
+        mode = "bf16_refined"
+    else:
+        Y = torch.from_numpy(pr["y"]).cuda()
+        mode = "native"
+    A0 = [torch.tensor(M, dtype=tdt).cuda() for M in pr["init"]]
+    A = [M.clone() for M in A0]
+    G = [torch.empty_like(M) for M in A]
+    plan = P.cpgrad_plan(dims, R, pr["storage"], fst, mode)
+    info = P.cpgrad_plan_info(plan)
+    P.cpgrad_bind(plan, Y)
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        P.cpgrad_all_modes(plan, Y, A, G)
+        P.cpals_step(plan, Y, A, sync=False)
+    torch.cuda.synchronize()
+    # restart the sweeps from the seeded initial factors so the timed sweeps are reproducible
+    for a, a0 in zip(A, A0):
+        a.copy_(a0)
+    P.cpgrad_set_option(plan, P.CPG_OPT_PROFILE, 1)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        ev[s][0].record(stream)
+        P.cpgrad_all_modes(plan, Y, A, G)
+        ev[s][1].record(stream)
+        P.cpals_step(plan, Y, A, sync=False)
+        ev[s][2].record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    fused_ms, fused_n = P.cpgrad_profile_read(plan, 3)
+    P.cpgrad_set_option(plan, P.CPG_OPT_PROFILE, 0)
+    cost, fit = P.cpgrad_last_fit(plan)
+
+    grad_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / args.steps
+    als_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / args.steps
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    gflops = info["alg_flops"] / (grad_ms * 1e-3) / 1e9
+
+    # roofline of the dominant kernel: the fused contraction (one pass over Y)
+    ybytes = Y.numel() * Y.element_size()
+    fbytes = sum(M.numel() * M.element_size() for M in A)
+    alg_bytes_launch = ybytes + fbytes
+    k_ms = fused_ms / max(fused_n, 1)
+    achieved = alg_bytes_launch / (k_ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": round(gflops, 3),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if pr["storage"] == "f32" else pr["storage"],
+        "data": "synthetic",
+        "config": {"workload": w.name, "dims": list(dims), "rank": R, "snr_db": w.snr_db,
+                   "storage": pr["storage"], "mode": mode, "n_star": info["n_star"],
+                   "step": "cpgrad_all_modes + cpals_step"},
+        "all_mode_gradient_ms": round(grad_ms, 5),
+        "als_iters_per_s": round(1e3 / als_ms, 2),
+        "als_sweep_ms": round(als_ms, 5),
+        "fit_after_timed_sweeps": fit,
+        "alg_flops_all_modes": info["alg_flops"],
+        "roofline": {"bound": "hbm", "kernel": "fused contraction (both partials, one pass over Y)",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "avg_launch_ms": round(k_ms, 6), "launches": fused_n,
+                     "alg_bytes_per_launch": alg_bytes_launch},
+    }
+    if not args.no_cpu_baseline:
+        dt, reps, cores = cpu_baseline(pr, args.cpu_budget_s)
+        out["cpu_baseline"] = {"value": round(info["alg_flops"] / dt / 1e9, 4), "unit": "GFLOP/s", "cores": cores,
+                               "kind": "oracle",
+                               "sample": f"{reps} whole all-mode gradient(s) of the same tensor by the float64 "
+                                         f"oracle (Algorithm 1 per mode), {dt:.3f} s each"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

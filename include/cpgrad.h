@@ -23,6 +23,8 @@
  *   G[n] : I_n x R, row-major, element type factor_dtype.
  *   The pointer arrays A and G themselves are HOST arrays of N device
  *   pointers.  The library never frees or reallocates caller memory.
+ *   Y must be 16-byte aligned (any fresh torch or hipMalloc allocation is);
+ *   a misaligned Y is rejected with CPG_ERR_INVALID.
  *
  * Supported type combinations
  *   y_dtype  factor_dtype  mode
@@ -79,8 +81,11 @@ typedef enum {
     CPG_OPT_FORCE_NSTAR = 1,   /* value in [1, N-1]: use this split instead of Algorithm
                                   2's n* (any split gives the same gradients, eqs. 3.7 =
                                   3.8); 0 restores the default                         */
-    CPG_OPT_KERNEL = 2         /* 0 = automatic, 1 = force the generic vector-ALU
+    CPG_OPT_KERNEL = 2,        /* 0 = automatic, 1 = force the generic vector-ALU
                                   contraction, 2 = force the MFMA contraction           */
+    CPG_OPT_PROFILE = 3        /* 1: bracket every big-contraction launch with a pair of
+                                  HIP events on the plan's stream (read them with
+                                  cpgrad_profile_read); 0: off (default)               */
 } cpg_option;
 
 /* Create a plan for tensors of shape dims[0..N-1] (dims[0] = I_1 is the fastest
@@ -108,6 +113,13 @@ int cpgrad_query(int N, const int64_t* dims, int R, int y_dtype, int factor_dtyp
 
 /* Set a plan option (cpg_option).  Re-tiles the plan if needed. */
 int cpgrad_set_option(cpgrad_plan_t p, int option, int64_t value);
+
+/* With CPG_OPT_PROFILE on: wait for the plan's stream and return the summed
+ * duration (milliseconds, HIP events) and the number of big-contraction
+ * launches recorded since the last read, restricted to `roles` (1 = right
+ * pass, 2 = left pass, 3 = fused all-mode pass, 0 = all); then clear the
+ * records.  Errors: CPG_ERR_INVALID, CPG_ERR_HIP. */
+int cpgrad_profile_read(cpgrad_plan_t p, int roles, double* total_ms, int64_t* launches);
 
 /* Bind a tensor: computes ||Y||_F^2 in float64 (needed by the cost of eq.
  * 2.12) and remembers the pointer; cpals_step and cp_fit must be called with

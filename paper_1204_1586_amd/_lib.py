@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_PKG, "libcpgrad.so")
 
 CPG_F64, CPG_F32, CPG_BF16 = 0, 1, 2
 CPG_MODE_NATIVE, CPG_MODE_BF16, CPG_MODE_BF16_REFINED = 0, 1, 2
-CPG_OPT_FORCE_NSTAR, CPG_OPT_KERNEL = 1, 2
+CPG_OPT_FORCE_NSTAR, CPG_OPT_KERNEL, CPG_OPT_PROFILE = 1, 2, 3
 MAX_MODES, MAX_RANK = 16, 64
 
 STATUS = {0: "CPG_OK", -1: "CPG_ERR_INVALID", -2: "CPG_ERR_NOMEM", -3: "CPG_ERR_HIP", -4: "CPG_ERR_NOT_SPD",
@@ -27,7 +27,7 @@ DTYPES = {"f64": CPG_F64, "f32": CPG_F32, "bf16": CPG_BF16}
 MODES = {"native": CPG_MODE_NATIVE, "bf16": CPG_MODE_BF16, "bf16_refined": CPG_MODE_BF16_REFINED}
 TORCH_DTYPE = {CPG_F64: torch.float64, CPG_F32: torch.float32, CPG_BF16: torch.bfloat16}
 
-EXPORTS = ["cpgrad_plan", "cpgrad_plan_info", "cpgrad_query", "cpgrad_set_option", "cpgrad_bind", "cpgrad_all_modes",
+EXPORTS = ["cpgrad_plan", "cpgrad_plan_info", "cpgrad_query", "cpgrad_set_option", "cpgrad_profile_read", "cpgrad_bind", "cpgrad_all_modes",
            "cpals_step", "cp_fit", "cpgrad_last_fit", "cpgrad_destroy", "cpgrad_status_string",
            "cpgrad_version"]
 
@@ -52,6 +52,7 @@ def _load():
         "cpgrad_query": (ctypes.c_int, [ctypes.c_int, i64p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_int), dp, dp]),
         "cpgrad_set_option": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int64]),
+        "cpgrad_profile_read": (ctypes.c_int, [vp, ctypes.c_int, dp, ctypes.POINTER(ctypes.c_int64)]),
         "cpgrad_bind": (ctypes.c_int, [vp, vp]),
         "cpgrad_all_modes": (ctypes.c_int, [vp, vp, ctypes.POINTER(vp), ctypes.POINTER(vp)]),
         "cpals_step": (ctypes.c_int, [vp, vp, ctypes.POINTER(vp), dp, dp]),
@@ -170,6 +171,14 @@ def cpgrad_query(dims, R, y_dtype="f32", factor_dtype=None, force_nstar=0):
 
 def cpgrad_set_option(plan, option, value):
     _check(LIB.cpgrad_set_option(plan.handle, int(option), int(value)), "cpgrad_set_option")
+
+
+def cpgrad_profile_read(plan, roles=0):
+    """(total_ms, launches) of the big-contraction launches timed since the last read."""
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    _check(LIB.cpgrad_profile_read(plan.handle, int(roles), ctypes.byref(ms), ctypes.byref(n)),
+           "cpgrad_profile_read")
+    return ms.value, n.value
 
 
 def cpgrad_bind(plan, Y):

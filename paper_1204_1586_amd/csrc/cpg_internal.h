@@ -20,6 +20,38 @@ struct FacSet {
     const T* A[CPG_MAX_MODES];
 };
 
+// One side of the peel-off of Algorithm 2 run by a single block (the chain
+// epilogue): for the modes n_first, n_first -/+ 1, ... (right chain going
+// down, left chain going up) it forms each mode's gradient from its chain
+// tensor (cp_gradient 'right' / 'left'), then either writes it to Gout or
+// applies eq. 2.14 to that factor, and steps the chain (eqs. 3.20, 3.22).
+template <typename TC>
+struct EpiArgs {
+    FacSet<TC> fs;                 // factors; updated in place when `update`
+    int side;                      // 0 = right chain (modes n_first, n_first-1, ...), 1 = left chain
+    int n_first;                   // paper's 1-based first mode
+    int n_count;                   // number of modes processed
+    const TC* Z;                   // chain tensor of mode n_first (R^(n) rows J_n, or L^(n) rows K_{n-1})
+    TC* buf[2];                    // chain ping-pong buffers
+    const TC* Gpre;                // if set: gradient of mode n_first given (Z unused for it)
+    TC* Gout[CPG_MAX_MODES];       // gradients out (when !update), by 0-based mode
+    int ld;                        // row stride of Z and the chain buffers
+    int update;                    // apply eq. 2.14 after each gradient
+    int init;                      // first: all float64 Grams, clear flags
+    int cost;                      // last: cost of eq. 2.12 and fit from G^(N)
+    double* grams;                 // [N][R][R] float64
+    double* scal;                  // [0] = ||Y||^2 in; [2] cost, [3] fit, [4] <Y,Yhat>, [5] ||Yhat||^2 out
+    int* flags;                    // bit 0: not SPD, bit 1: non-finite cost
+    int64_t Jn[CPG_MAX_MODES + 1];
+    int64_t Kn[CPG_MAX_MODES + 1];
+};
+
+constexpr int kEpiGCap = 4096;     // largest I_n * (padded R) the epilogue keeps in LDS
+constexpr int kEpiKRCap = 4096;    // largest (terms x ld) of Khatri-Rao rows / factor entries it stages
+
+// Launch `nsides` (1 or 2) epilogue blocks; args[b] drives block b.
+hipError_t launch_epilogue(int fdt, int R, const void* args, int nsides, hipStream_t stream);
+
 // Tiling of one contraction pass over the J x K view Y_(1:n*).
 struct Tiling {
     int kernel;        // 1 = generic vector ALU, 2 = MFMA
@@ -33,28 +65,37 @@ struct Tiling {
 // Launchers (defined in the kernel translation units).  All enqueue on
 // `stream` and return a hipError_t.
 //   roles: bit 0 = right contraction (P_R partials), bit 1 = left (P_L partials)
-//   PRpart: [n_kc][J][R], PLpart: [n_jr][K][R]   (accumulation type)
+//   PRpart: [n_kc][J][ld], PLpart: [n_jr][K][ld]   (accumulation type)
+// Every internal chain buffer (P_R, P_L, chain tensors, partials) stores its
+// rows with the padded stride ld = 4 * ceil(R / 4); entries r >= R of a row are
+// never read into a result.
 hipError_t launch_contract_valu(int ydt, int fdt, const void* Y, int64_t J, int64_t K,
-                                const void* facset, int nstar, const Tiling& t, int roles,
+                                const void* facset, int nstar, const Tiling& t, int roles, int ld,
                                 void* PRpart, void* PLpart, hipStream_t stream);
+// Outputs of the MFMA contraction: the split partials.
+struct MfmaOut {
+    float* PRpart;
+    float* PLpart;
+    int ld;      // row stride (padded rank) of the partials
+};
 hipError_t launch_contract_mfma(int ydt, int mode, const void* Y, int64_t J, int64_t K,
                                 const FacSet<float>& fs, int nstar, const Tiling& t, int roles,
-                                float* PRpart, float* PLpart, hipStream_t stream);
+                                const MfmaOut& out, hipStream_t stream);
 bool mfma_supported(int ydt, int fdt, int mode, int R);
 
-// out[row][r] = sum_p parts[p][row][r]  (summed in float64, fixed order)
-hipError_t launch_reduce_parts(int fdt, const void* parts, int64_t nparts, int64_t rows, int R,
+// out[row][r] = sum_p parts[p][row][r] over rows x ld entries (float64, fixed order)
+hipError_t launch_reduce_parts(int fdt, const void* parts, int64_t nparts, int64_t rows, int ld,
                                void* out, hipStream_t stream);
 
 // mode product along the middle index of a (lo_n, I, hi_n) row space:
 // out[lo + lo_n*hi][r] = sum_i in[lo + lo_n*(i + I*hi)][r] * a[i][r]
 hipError_t launch_ttv(int fdt, const void* in, void* out, const void* a, int64_t lo_n, int64_t I,
-                      int64_t hi_n, int R, hipStream_t stream);
+                      int64_t hi_n, int R, int ld, hipStream_t stream);
 
 // G(i, r) = sum_{lo, hi} Z[lo + lo_n*(i + I*hi)][r] * KR_lo(lo, r) * KR_hi(hi, r)
 // KR_lo runs over modes [lo_first, lo_first+lo_count), KR_hi over
 // [hi_first, hi_first+hi_count) (first listed mode fastest).
-hipError_t launch_grad(int fdt, const void* Z, void* G, const void* facset, int64_t lo_n, int64_t I,
+hipError_t launch_grad(int fdt, const void* Z, int ld, void* G, const void* facset, int64_t lo_n, int64_t I,
                        int64_t hi_n, int lo_first, int lo_count, int hi_first, int hi_count,
                        hipStream_t stream);
 
@@ -71,7 +112,7 @@ hipError_t launch_norm2(int ydt, const void* Y, int64_t n, double* scratch, doub
                         hipStream_t stream);
 
 // inner = sum_{j<J, r} PR[j][r] * KR_left(j, r) (modes 0..nstar-1) -> *out
-hipError_t launch_inner_kr(int fdt, const void* PR, int64_t J, const void* facset, int nstar,
+hipError_t launch_inner_kr(int fdt, const void* PR, int ld, int64_t J, const void* facset, int nstar,
                            double* scratch, double* out, hipStream_t stream);
 
 // cost and fit in float64.  If G is non-null, inner = sum G .* A (I x R);

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "cpg_internal.h"
 
@@ -14,6 +15,7 @@ using namespace cpg;
 
 struct cpgrad_plan_s {
     int N = 0, R = 0;
+    int ld = 4;                            // row stride of internal chain buffers: 4 * ceil(R / 4)
     int64_t dims[CPG_MAX_MODES] = {0};
     int ydt = 0, fdt = 0, mode = 0;
     hipStream_t stream = nullptr;
@@ -29,7 +31,7 @@ struct cpgrad_plan_s {
     size_t ws_bytes = 0;
     void* PR = nullptr;
     void* PL = nullptr;
-    void* chain[2] = {nullptr, nullptr};
+    void* chain[4] = {nullptr, nullptr, nullptr, nullptr};
     void* PRpart = nullptr;
     void* PLpart = nullptr;
     void* Gtmp = nullptr;
@@ -39,6 +41,11 @@ struct cpgrad_plan_s {
     int* flags = nullptr;
     double* host = nullptr;   // pinned readback: scal[0..7], flags
     const void* bound = nullptr;
+    // optional HIP-event timing of the big contraction launches
+    int profile = 0;
+    std::vector<hipEvent_t> ev_start, ev_stop;
+    std::vector<int> ev_roles;
+    size_t ev_used = 0;
 };
 
 namespace {
@@ -77,8 +84,29 @@ static Tiling tile_valu(int64_t J, int64_t K, int R, int fdt, int roles) {
     return t;
 }
 
-static Tiling tile_pass(const cpgrad_plan_s* p, int roles) {
+// Tiling of one pass for the MFMA kernel: 256-row blocks, column chunks of
+// whole 32-column steps, about two blocks per compute unit.
+static Tiling tile_mfma(int64_t J, int64_t K, int R, int roles) {
+    Tiling t{};
+    t.kernel = 2;
+    t.rt = 16 * (int)cdiv(R, 16);
+    t.jtb = 1;
+    t.n_jr = cdiv(J, 256);
+    const int64_t steps = cdiv(K, 32);
+    const int64_t target = 512;
     (void)roles;
+    t.ktb = std::max<int64_t>(1, cdiv(steps * t.n_jr, target));
+    t.n_kc = cdiv(steps, t.ktb);
+    return t;
+}
+
+static bool use_mfma(const cpgrad_plan_s* p) {
+    if (p->kernel_opt == 1) return false;
+    return mfma_supported(p->ydt, p->fdt, p->mode, p->R) && (p->J % 4) == 0 && p->J < (int64_t(1) << 31);
+}
+
+static Tiling tile_pass(const cpgrad_plan_s* p, int roles) {
+    if (use_mfma(p)) return tile_mfma(p->J, p->K, p->R, roles);
     return tile_valu(p->J, p->K, p->R, p->fdt, roles);
 }
 
@@ -99,7 +127,7 @@ static int configure(cpgrad_plan_s* p) {
     p->t_fused = tile_pass(p, 3);
     p->t_right = tile_pass(p, 1);
     p->t_left = tile_pass(p, 2);
-    const size_t a = p->acc, R = (size_t)p->R;
+    const size_t a = p->acc, R = (size_t)p->ld;
     int64_t chain_rows = 0;
     if (p->nstar >= 2) chain_rows = std::max<int64_t>(chain_rows, p->Jn[p->nstar - 1]);
     if (p->nstar + 1 < N) chain_rows = std::max<int64_t>(chain_rows, p->Kn[p->nstar + 1]);
@@ -113,10 +141,12 @@ static int configure(cpgrad_plan_s* p) {
     const size_t oPL = off;     off += al(p->K * R * a);
     const size_t oC0 = off;     off += al(chain_rows * R * a);
     const size_t oC1 = off;     off += al(chain_rows * R * a);
+    const size_t oC2 = off;     off += al(chain_rows * R * a);
+    const size_t oC3 = off;     off += al(chain_rows * R * a);
     const size_t oPRp = off;    off += al(nkc * p->J * R * a);
     const size_t oPLp = off;    off += al(njr * p->K * R * a);
     const size_t oG = off;      off += al(maxI * R * a);
-    const size_t oGr = off;     off += al((size_t)N * R * R * 8);
+    const size_t oGr = off;     off += al((size_t)N * p->R * p->R * 8);
     const size_t oS = off;      off += al(16 * 8);
     const size_t oRed = off;    off += al(kRedScratch * 8);
     const size_t oF = off;      off += al(16 * sizeof(int));
@@ -135,6 +165,8 @@ static int configure(cpgrad_plan_s* p) {
     p->PL = b + oPL;
     p->chain[0] = b + oC0;
     p->chain[1] = b + oC1;
+    p->chain[2] = b + oC2;
+    p->chain[3] = b + oC3;
     p->PRpart = b + oPRp;
     p->PLpart = b + oPLp;
     p->Gtmp = b + oG;
@@ -142,6 +174,7 @@ static int configure(cpgrad_plan_s* p) {
     p->scal = (double*)(b + oS);
     p->red = (double*)(b + oRed);
     p->flags = (int*)(b + oF);
+
     if (hipMemsetAsync(p->scal, 0, 16 * 8, p->stream) != hipSuccess) return CPG_ERR_HIP;
     if (hipMemsetAsync(p->flags, 0, 16 * sizeof(int), p->stream) != hipSuccess) return CPG_ERR_HIP;
     p->bound = nullptr;
@@ -176,12 +209,39 @@ static AnyFacSet facsets(const cpgrad_plan_s* p, const void* const* A) {
     return s;
 }
 
+static hipError_t launch_contract(cpgrad_plan_s* p, const void* Y, const AnyFacSet& fs, const Tiling& t,
+                                  int roles) {
+    if (t.n_kc > 65535) return hipErrorInvalidConfiguration;
+    if (t.kernel == 2) {
+        MfmaOut o{(float*)p->PRpart, (float*)p->PLpart, p->ld};
+        return launch_contract_mfma(p->ydt, p->mode, Y, p->J, p->K, fs.f, p->nstar, t, roles, o, p->stream);
+    }
+    return launch_contract_valu(p->ydt, p->fdt, Y, p->J, p->K, fs.ptr(p->fdt), p->nstar, t, roles, p->ld,
+                                p->PRpart, p->PLpart, p->stream);
+}
+
+// Launch one big contraction; with profiling on, bracket it with HIP events
+// recorded on the plan's stream.
 static hipError_t run_contract(cpgrad_plan_s* p, const void* Y, const AnyFacSet& fs, const Tiling& t, int roles) {
-    if (t.kernel == 2)
-        return launch_contract_mfma(p->ydt, p->mode, Y, p->J, p->K, fs.f, p->nstar, t, roles, (float*)p->PRpart,
-                                    (float*)p->PLpart, p->stream);
-    return launch_contract_valu(p->ydt, p->fdt, Y, p->J, p->K, fs.ptr(p->fdt), p->nstar, t, roles, p->PRpart,
-                                p->PLpart, p->stream);
+    if (!p->profile) return launch_contract(p, Y, fs, t, roles);
+    if (p->ev_used == p->ev_start.size()) {
+        if (p->ev_used >= 65536) return launch_contract(p, Y, fs, t, roles);  // pool full: stop recording
+        hipEvent_t a, b;
+        hipError_t e = hipEventCreate(&a);
+        if (e != hipSuccess) return e;
+        e = hipEventCreate(&b);
+        if (e != hipSuccess) return e;
+        p->ev_start.push_back(a);
+        p->ev_stop.push_back(b);
+        p->ev_roles.push_back(0);
+    }
+    const size_t i = p->ev_used++;
+    p->ev_roles[i] = roles;
+    hipError_t e = hipEventRecord(p->ev_start[i], p->stream);
+    if (e != hipSuccess) return e;
+    e = launch_contract(p, Y, fs, t, roles);
+    if (e != hipSuccess) return e;
+    return hipEventRecord(p->ev_stop[i], p->stream);
 }
 
 #define CPG_TRY(x)                                   \
@@ -192,29 +252,159 @@ static hipError_t run_contract(cpgrad_plan_s* p, const void* Y, const AnyFacSet&
 
 // Reduce the partials of a pass into P_R and/or P_L.
 static int finish_partials(cpgrad_plan_s* p, const Tiling& t, int roles) {
-    if (roles & 1) CPG_TRY(launch_reduce_parts(p->fdt, p->PRpart, t.n_kc, p->J, p->R, p->PR, p->stream));
-    if (roles & 2) CPG_TRY(launch_reduce_parts(p->fdt, p->PLpart, t.n_jr, p->K, p->R, p->PL, p->stream));
+    if (roles & 1) CPG_TRY(launch_reduce_parts(p->fdt, p->PRpart, t.n_kc, p->J, p->ld, p->PR, p->stream));
+    if (roles & 2) CPG_TRY(launch_reduce_parts(p->fdt, p->PLpart, t.n_jr, p->K, p->ld, p->PL, p->stream));
     return CPG_OK;
 }
 
-// Right chain of Algorithm 2 (steps 4-5 and 9-12): modes n*, ..., 1.
-// If `update`, eq. 2.14 is applied to each mode right after its gradient and
-// the next chain step uses the updated factor; otherwise G[n] receives the
-// gradient.
+// Chain tensors bigger than this go through the multi-block grad / ttv
+// kernels for their first step; smaller ones are walked by one epilogue block.
+constexpr size_t kEpiLargeBytes = size_t(2) << 20;
+
+static int epi_rank_tile(int R) { return rank_tile(R); }
+
+// Terms of the gradient of paper mode n from its chain tensor: J_{n-1} on the
+// right side (n <= n*), K_n on the left side.
+static int64_t grad_terms(const cpgrad_plan_s* p, int n) { return n <= p->nstar ? p->Jn[n - 1] : p->Kn[n]; }
+
+// Does the first mode of a side go through the single-block epilogue, or does
+// its chain tensor (or its Khatri-Rao block) call for the multi-block kernels?
+static bool side_first_small(const cpgrad_plan_s* p, int side, size_t elem) {
+    const int n = side == 0 ? p->nstar : p->nstar + 1;
+    const int64_t rows = side == 0 ? p->J : p->K;
+    return (size_t)rows * p->ld * elem <= kEpiLargeBytes && grad_terms(p, n) * p->ld <= kEpiKRCap;
+}
+
+// Can the single-block epilogue hold every mode's gradient, factor and the
+// Khatri-Rao blocks of every mode after the first of each side?
+static bool epilogue_fits(const cpgrad_plan_s* p) {
+    const int rt = epi_rank_tile(p->R);
+    for (int n = 0; n < p->N; ++n)
+        if (p->dims[n] * rt > kEpiGCap || p->dims[n] * p->ld > kEpiKRCap) return false;
+    for (int n = 1; n <= p->N; ++n) {
+        if (n == p->nstar || n == p->nstar + 1) continue;
+        if (grad_terms(p, n) * p->ld > kEpiKRCap) return false;
+    }
+    return true;
+}
+
+template <typename TC>
+static EpiArgs<TC> epi_base(const cpgrad_plan_s* p, const FacSet<TC>& fs) {
+    EpiArgs<TC> a{};
+    a.fs = fs;
+    a.grams = p->grams;
+    a.ld = p->ld;
+    a.scal = p->scal;
+    a.flags = p->flags;
+    for (int n = 0; n <= p->N; ++n) {
+        a.Jn[n] = p->Jn[n];
+        a.Kn[n] = p->Kn[n];
+    }
+    return a;
+}
+
+// One side of the peel-off (Algorithm 2 steps 4-5, 9-12 on the right, steps
+// 7-8, 13-16 on the left; with `update`, eq. 2.14 after each gradient in the
+// Section 4 order).  Small chain tensors: one epilogue block for the whole
+// side.  A large first chain tensor: its gradient and its chain step run on
+// the multi-block kernels, the rest in the epilogue.
+template <typename TC>
+static int run_side(cpgrad_plan_s* p, const FacSet<TC>& fs, int side, void* const* A, void* const* G, bool update,
+                    bool init, bool cost) {
+    const int N = p->N, R = p->R;
+    const int n_first = side == 0 ? p->nstar : p->nstar + 1;
+    const int n_count = side == 0 ? p->nstar : N - p->nstar;
+    const void* Z = side == 0 ? p->PR : p->PL;
+    const int64_t rows = side == 0 ? p->J : p->K;
+    EpiArgs<TC> a = epi_base<TC>(p, fs);
+    a.side = side;
+    a.update = update ? 1 : 0;
+    for (int n = 0; n < N; ++n) a.Gout[n] = G ? (TC*)G[n] : nullptr;
+    (void)rows;
+    if (side_first_small(p, side, sizeof(TC))) {
+        a.n_first = n_first;
+        a.n_count = n_count;
+        a.Z = (const TC*)Z;
+        a.buf[0] = (TC*)p->chain[0];
+        a.buf[1] = (TC*)p->chain[1];
+        a.init = init ? 1 : 0;
+        a.cost = cost ? 1 : 0;
+        CPG_TRY(launch_epilogue(p->fdt, R, &a, 1, p->stream));
+        return CPG_OK;
+    }
+    // first mode of the side on the multi-block kernels
+    const int n = n_first;
+    void* g = update ? p->Gtmp : G[n - 1];
+    if (side == 0)
+        CPG_TRY(launch_grad(p->fdt, Z, p->ld, g, &fs, p->Jn[n - 1], p->dims[n - 1], 1, 0, n - 1, 0, 0, p->stream));
+    else
+        CPG_TRY(launch_grad(p->fdt, Z, p->ld, g, &fs, 1, p->dims[n - 1], p->Kn[n], 0, 0, n, N - n, p->stream));
+    if (update || init) {
+        EpiArgs<TC> b = a;
+        b.n_first = n;
+        b.n_count = update ? 1 : 0;
+        b.Gpre = (const TC*)g;
+        b.init = init ? 1 : 0;
+        b.cost = (cost && n_count == 1) ? 1 : 0;
+        CPG_TRY(launch_epilogue(p->fdt, R, &b, 1, p->stream));
+    }
+    if (n_count == 1) return CPG_OK;
+    // next chain tensor with the (updated) factor, then the rest of the side
+    const int nn = side == 0 ? n - 1 : n + 1;
+    if (side == 0)
+        CPG_TRY(launch_ttv(p->fdt, Z, p->chain[0], A[nn], p->Jn[nn], p->dims[nn], 1, R, p->ld, p->stream));
+    else
+        CPG_TRY(launch_ttv(p->fdt, Z, p->chain[0], A[nn - 2], 1, p->dims[nn - 2], p->Kn[nn - 1], R, p->ld,
+                           p->stream));
+    EpiArgs<TC> c = a;
+    c.n_first = nn;
+    c.n_count = n_count - 1;
+    c.Z = (const TC*)p->chain[0];
+    c.buf[0] = (TC*)p->chain[1];
+    c.buf[1] = (TC*)p->chain[0];
+    c.cost = cost ? 1 : 0;
+    CPG_TRY(launch_epilogue(p->fdt, R, &c, 1, p->stream));
+    return CPG_OK;
+}
+
+template <typename TC>
+static int run_both_sides(cpgrad_plan_s* p, const FacSet<TC>& fs, void* const* A, void* const* G) {
+    if (side_first_small(p, 0, sizeof(TC)) && side_first_small(p, 1, sizeof(TC))) {
+        // both chains are independent without updates: one launch, two blocks
+        EpiArgs<TC> a[2] = {epi_base<TC>(p, fs), epi_base<TC>(p, fs)};
+        for (int s = 0; s < 2; ++s) {
+            a[s].side = s;
+            a[s].n_first = s == 0 ? p->nstar : p->nstar + 1;
+            a[s].n_count = s == 0 ? p->nstar : p->N - p->nstar;
+            a[s].Z = (const TC*)(s == 0 ? p->PR : p->PL);
+            a[s].buf[0] = (TC*)p->chain[2 * s];
+            a[s].buf[1] = (TC*)p->chain[2 * s + 1];
+            for (int n = 0; n < p->N; ++n) a[s].Gout[n] = (TC*)G[n];
+        }
+        CPG_TRY(launch_epilogue(p->fdt, p->R, a, 2, p->stream));
+        return CPG_OK;
+    }
+    int st = run_side<TC>(p, fs, 0, A, G, false, false, false);
+    if (st) return st;
+    // the left side reuses the chain buffers after the right side finished (stream order)
+    return run_side<TC>(p, fs, 1, A, G, false, false, false);
+}
+
+// Legacy per-kernel chains, used when a gradient does not fit the epilogue's LDS.
 static int right_chain(cpgrad_plan_s* p, const AnyFacSet& fs, void* const* A, void* const* G, bool update) {
     const void* cur = p->PR;
     int buf = 0;
     for (int n = p->nstar; n >= 1; --n) {          // paper's 1-based mode n
         if (n < p->nstar) {
             // vec R^(r,n) = reshape(R^(r,n+1), [J_n, I_{n+1}]) a_r^(n+1)   (eq. 3.20)
-            CPG_TRY(launch_ttv(p->fdt, cur, p->chain[buf], A[n], p->Jn[n], p->dims[n], 1, p->R, p->stream));
+            CPG_TRY(launch_ttv(p->fdt, cur, p->chain[buf], A[n], p->Jn[n], p->dims[n], 1, p->R, p->ld, p->stream));
             cur = p->chain[buf];
             buf ^= 1;
         }
         void* g = update ? p->Gtmp : G[n - 1];
         // g_r^(n) = reshape(R^(r,n), [J_{n-1}, I_n])^T (a_r^(n-1) (x) ... (x) a_r^(1))   (eq. 3.12)
-        CPG_TRY(launch_grad(p->fdt, cur, g, fs.ptr(p->fdt), p->Jn[n - 1], p->dims[n - 1], 1, 0, n - 1, 0, 0,
-                            p->stream));
+        CPG_TRY(launch_grad(p->fdt, cur, p->ld, g, fs.ptr(p->fdt), p->Jn[n - 1], p->dims[n - 1], 1, 0, n - 1, 0,
+                            0, p->stream));
         if (update)
             CPG_TRY(launch_als_update(p->fdt, g, A[n - 1], p->grams, p->N, n - 1, p->dims[n - 1], p->R, p->flags,
                                       p->stream));
@@ -222,7 +412,6 @@ static int right_chain(cpgrad_plan_s* p, const AnyFacSet& fs, void* const* A, vo
     return CPG_OK;
 }
 
-// Left chain of Algorithm 2 (steps 7-8 and 13-16): modes n*+1, ..., N.
 static int left_chain(cpgrad_plan_s* p, const AnyFacSet& fs, void* const* A, void* const* G, bool update) {
     const void* cur = p->PL;
     int buf = 0;
@@ -230,14 +419,14 @@ static int left_chain(cpgrad_plan_s* p, const AnyFacSet& fs, void* const* A, voi
         if (n > p->nstar + 1) {
             // vec L^(r,n) = reshape(L^(r,n-1), [I_{n-1}, K_{n-1}])^T a_r^(n-1)   (eq. 3.22)
             CPG_TRY(launch_ttv(p->fdt, cur, p->chain[buf], A[n - 2], 1, p->dims[n - 2], p->Kn[n - 1], p->R,
-                               p->stream));
+                               p->ld, p->stream));
             cur = p->chain[buf];
             buf ^= 1;
         }
         void* g = update ? p->Gtmp : G[n - 1];
         // g_r^(n) = reshape(L^(r,n), [I_n, K_n]) (a_r^(N) (x) ... (x) a_r^(n+1))   (eq. 3.16)
-        CPG_TRY(launch_grad(p->fdt, cur, g, fs.ptr(p->fdt), 1, p->dims[n - 1], p->Kn[n], 0, 0, n, p->N - n,
-                            p->stream));
+        CPG_TRY(launch_grad(p->fdt, cur, p->ld, g, fs.ptr(p->fdt), 1, p->dims[n - 1], p->Kn[n], 0, 0, n,
+                            p->N - n, p->stream));
         if (update)
             CPG_TRY(launch_als_update(p->fdt, g, A[n - 1], p->grams, p->N, n - 1, p->dims[n - 1], p->R, p->flags,
                                       p->stream));
@@ -359,6 +548,7 @@ int cpgrad_plan(cpgrad_plan_t* out, int N, const int64_t* dims, int R, int y_dty
     if (!p) return CPG_ERR_NOMEM;
     p->N = N;
     p->R = R;
+    p->ld = 4 * ((R + 3) / 4);
     for (int n = 0; n < N; ++n) p->dims[n] = dims[n];
     p->ydt = y_dtype;
     p->fdt = factor_dtype;
@@ -410,8 +600,32 @@ int cpgrad_plan_info(cpgrad_plan_t p, int* n_star, size_t* workspace_bytes, doub
     return CPG_OK;
 }
 
+int cpgrad_profile_read(cpgrad_plan_t p, int roles, double* total_ms, int64_t* launches) {
+    if (!p || roles < 0 || roles > 3) return CPG_ERR_INVALID;
+    if (hipStreamSynchronize(p->stream) != hipSuccess) return CPG_ERR_HIP;
+    double tot = 0.0;
+    int64_t cnt = 0;
+    for (size_t i = 0; i < p->ev_used; ++i) {
+        if (roles != 0 && p->ev_roles[i] != roles) continue;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p->ev_start[i], p->ev_stop[i]) != hipSuccess) return CPG_ERR_HIP;
+        tot += ms;
+        ++cnt;
+    }
+    p->ev_used = 0;
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = cnt;
+    return CPG_OK;
+}
+
 int cpgrad_set_option(cpgrad_plan_t p, int option, int64_t value) {
     if (!p) return CPG_ERR_INVALID;
+    if (option == CPG_OPT_PROFILE) {
+        if (value < 0 || value > 1) return CPG_ERR_INVALID;
+        p->profile = (int)value;
+        p->ev_used = 0;
+        return CPG_OK;
+    }
     if (option == CPG_OPT_FORCE_NSTAR) {
         if (value != 0 && (value < 1 || value > p->N - 1)) return CPG_ERR_INVALID;
         p->force_nstar = (int)value;
@@ -429,6 +643,7 @@ int cpgrad_set_option(cpgrad_plan_t p, int option, int64_t value) {
 
 int cpgrad_bind(cpgrad_plan_t p, const void* Y) {
     if (!p || !Y) return CPG_ERR_INVALID;
+    if (((uintptr_t)Y & 15) != 0) return CPG_ERR_INVALID;
     if (launch_norm2(p->ydt, Y, p->numel, p->red, p->scal, p->stream) != hipSuccess) return CPG_ERR_HIP;
     p->bound = Y;
     return CPG_OK;
@@ -436,12 +651,17 @@ int cpgrad_bind(cpgrad_plan_t p, const void* Y) {
 
 int cpgrad_all_modes(cpgrad_plan_t p, const void* Y, const void* const* A, void* const* G) {
     if (!p || !Y || !A || !G) return CPG_ERR_INVALID;
+    if (((uintptr_t)Y & 15) != 0) return CPG_ERR_INVALID;
     for (int n = 0; n < p->N; ++n)
         if (!A[n] || !G[n]) return CPG_ERR_INVALID;
     const AnyFacSet fs = facsets(p, A);
     CPG_TRY(run_contract(p, Y, fs, p->t_fused, 3));
     int st = finish_partials(p, p->t_fused, 3);
     if (st) return st;
+    if (epilogue_fits(p)) {
+        if (p->fdt == CPG_F64) return run_both_sides<double>(p, fs.d, (void* const*)A, G);
+        return run_both_sides<float>(p, fs.f, (void* const*)A, G);
+    }
     st = right_chain(p, fs, (void* const*)A, G, false);
     if (st) return st;
     return left_chain(p, fs, (void* const*)A, G, false);
@@ -453,24 +673,37 @@ int cpals_step(cpgrad_plan_t p, const void* Y, void* const* A, double* cost_out,
     for (int n = 0; n < p->N; ++n)
         if (!A[n]) return CPG_ERR_INVALID;
     const AnyFacSet fs = facsets(p, (const void* const*)A);
-    hipLaunchKernelGGL(k_zero_flags, dim3(1), dim3(64), 0, p->stream, p->flags);
-    CPG_TRY(hipGetLastError());
-    CPG_TRY(launch_grams(p->fdt, fs.ptr(p->fdt), p->grams, p->stream));
+    const bool epi = epilogue_fits(p);
+    if (!epi) {
+        hipLaunchKernelGGL(k_zero_flags, dim3(1), dim3(64), 0, p->stream, p->flags);
+        CPG_TRY(hipGetLastError());
+        CPG_TRY(launch_grams(p->fdt, fs.ptr(p->fdt), p->grams, p->stream));
+    }
     // pass 1 over Y: P_R with the current A^(n*+1..N), then modes n*, ..., 1
     CPG_TRY(run_contract(p, Y, fs, p->t_right, 1));
     int st = finish_partials(p, p->t_right, 1);
     if (st) return st;
-    st = right_chain(p, fs, A, nullptr, true);
+    if (epi)
+        st = p->fdt == CPG_F64 ? run_side<double>(p, fs.d, 0, A, nullptr, true, true, false)
+                               : run_side<float>(p, fs.f, 0, A, nullptr, true, true, false);
+    else
+        st = right_chain(p, fs, A, nullptr, true);
     if (st) return st;
-    // pass 2 over Y: P_L with the updated A^(1..n*), then modes n*+1, ..., N
+    // pass 2 over Y: P_L with the updated A^(1..n*), then modes n*+1, ..., N and the cost
     CPG_TRY(run_contract(p, Y, fs, p->t_left, 2));
     st = finish_partials(p, p->t_left, 2);
     if (st) return st;
-    st = left_chain(p, fs, A, nullptr, true);
-    if (st) return st;
-    // cost of eq. 2.12: Gtmp holds G^(N) (taken before the A^(N) update)
-    CPG_TRY(launch_cost_fit(p->fdt, p->Gtmp, A[p->N - 1], p->dims[p->N - 1], p->R, nullptr, p->grams, p->N,
-                            p->scal, p->flags, p->stream));
+    if (epi) {
+        st = p->fdt == CPG_F64 ? run_side<double>(p, fs.d, 1, A, nullptr, true, false, true)
+                               : run_side<float>(p, fs.f, 1, A, nullptr, true, false, true);
+        if (st) return st;
+    } else {
+        st = left_chain(p, fs, A, nullptr, true);
+        if (st) return st;
+        // cost of eq. 2.12: Gtmp holds G^(N) (taken before the A^(N) update)
+        CPG_TRY(launch_cost_fit(p->fdt, p->Gtmp, A[p->N - 1], p->dims[p->N - 1], p->R, nullptr, p->grams, p->N,
+                                p->scal, p->flags, p->stream));
+    }
     if (!cost_out && !fit_out) return CPG_OK;
     return readback(p, cost_out, fit_out);
 }
@@ -487,7 +720,8 @@ int cp_fit(cpgrad_plan_t p, const void* Y, const void* const* A, double* cost_ou
     CPG_TRY(run_contract(p, Y, fs, p->t_right, 1));
     int st = finish_partials(p, p->t_right, 1);
     if (st) return st;
-    CPG_TRY(launch_inner_kr(p->fdt, p->PR, p->J, fs.ptr(p->fdt), p->nstar, p->red, p->scal + 6, p->stream));
+    CPG_TRY(launch_inner_kr(p->fdt, p->PR, p->ld, p->J, fs.ptr(p->fdt), p->nstar, p->red, p->scal + 6,
+                            p->stream));
     CPG_TRY(launch_cost_fit(p->fdt, nullptr, nullptr, 0, p->R, p->scal + 6, p->grams, p->N, p->scal, p->flags,
                             p->stream));
     return readback(p, cost_out, fit_out);
@@ -504,6 +738,10 @@ int cpgrad_destroy(cpgrad_plan_t p) {
     else (void)hipDeviceSynchronize();
     release(p);
     if (p->host) (void)hipHostFree(p->host);
+    for (size_t i = 0; i < p->ev_start.size(); ++i) {
+        (void)hipEventDestroy(p->ev_start[i]);
+        (void)hipEventDestroy(p->ev_stop[i]);
+    }
     delete p;
     return CPG_OK;
 }

@@ -5,22 +5,9 @@
 //  * float64 Gram matrices, the Cholesky solve of eq. 2.14, ||Y||^2, and the
 //    cost of eq. 2.12 with fit = 1 - ||Y - Yhat|| / ||Y||.
 // All reductions run in a fixed order, so results are bitwise reproducible.
-#include "cpg_internal.h"
+#include "cpg_device.h"
 
 namespace cpg {
-
-template <typename TC>
-__device__ __forceinline__ double kr_entry_d(const FacSet<TC>& fs, int first, int count, int64_t idx, int r) {
-    double v = 1.0;
-    for (int m = 0; m < count; ++m) {
-        const int64_t d = fs.dims[first + m];
-        const int64_t q = idx / d;
-        const int64_t i = idx - q * d;
-        idx = q;
-        v *= (double)fs.A[first + m][i * fs.R + r];
-    }
-    return v;
-}
 
 __device__ __forceinline__ double block_sum_256(double v, double* sbuf) {
     // sbuf: >= 256 doubles; returns the total in every thread
@@ -45,13 +32,21 @@ __global__ __launch_bounds__(256) void k_reduce_parts(const TC* __restrict__ par
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (e >= n) return;
     double acc = 0.0;
-    for (int64_t p = 0; p < nparts; ++p) acc += (double)parts[p * n + e];
+    int64_t p = 0;
+    for (; p + 8 <= nparts; p += 8) {
+        TC v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = parts[(p + u) * n + e];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += (double)v[u];
+    }
+    for (; p < nparts; ++p) acc += (double)parts[p * n + e];
     out[e] = (TC)acc;
 }
 
-hipError_t launch_reduce_parts(int fdt, const void* parts, int64_t nparts, int64_t rows, int R, void* out,
+hipError_t launch_reduce_parts(int fdt, const void* parts, int64_t nparts, int64_t rows, int ld, void* out,
                                hipStream_t s) {
-    const int64_t n = rows * R;
+    const int64_t n = rows * ld;
     const unsigned nb = (unsigned)((n + 255) / 256);
     if (fdt == CPG_F64)
         hipLaunchKernelGGL(k_reduce_parts<double>, dim3(nb), dim3(256), 0, s, (const double*)parts, nparts, n,
@@ -70,28 +65,37 @@ hipError_t launch_reduce_parts(int fdt, const void* parts, int64_t nparts, int64
 template <typename TC>
 __global__ __launch_bounds__(256) void k_ttv(const TC* __restrict__ in, TC* __restrict__ out,
                                              const TC* __restrict__ a, int64_t lo_n, int64_t I, int64_t hi_n,
-                                             int R) {
+                                             int R, int ld) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (e >= lo_n * hi_n * R) return;
     const int64_t row = e / R;
     const int r = (int)(e - row * R);
     const int64_t hi = row / lo_n;
     const int64_t lo = row - hi * lo_n;
-    double acc = 0.0;
-    for (int64_t i = 0; i < I; ++i) acc += (double)in[(lo + lo_n * (i + I * hi)) * R + r] * (double)a[i * R + r];
-    out[e] = (TC)acc;
+    const TC* src = in + (lo + lo_n * I * hi) * ld + r;
+    const int64_t step = lo_n * ld;
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+    int64_t i = 0;
+    for (; i + 4 <= I; i += 4) {
+        acc0 += (double)src[(i + 0) * step] * (double)a[(i + 0) * R + r];
+        acc1 += (double)src[(i + 1) * step] * (double)a[(i + 1) * R + r];
+        acc2 += (double)src[(i + 2) * step] * (double)a[(i + 2) * R + r];
+        acc3 += (double)src[(i + 3) * step] * (double)a[(i + 3) * R + r];
+    }
+    for (; i < I; ++i) acc0 += (double)src[i * step] * (double)a[i * R + r];
+    out[row * ld + r] = (TC)((acc0 + acc1) + (acc2 + acc3));
 }
 
 hipError_t launch_ttv(int fdt, const void* in, void* out, const void* a, int64_t lo_n, int64_t I, int64_t hi_n,
-                      int R, hipStream_t s) {
+                      int R, int ld, hipStream_t s) {
     const int64_t n = lo_n * hi_n * R;
     const unsigned nb = (unsigned)((n + 255) / 256);
     if (fdt == CPG_F64)
         hipLaunchKernelGGL(k_ttv<double>, dim3(nb), dim3(256), 0, s, (const double*)in, (double*)out,
-                           (const double*)a, lo_n, I, hi_n, R);
+                           (const double*)a, lo_n, I, hi_n, R, ld);
     else
         hipLaunchKernelGGL(k_ttv<float>, dim3(nb), dim3(256), 0, s, (const float*)in, (float*)out,
-                           (const float*)a, lo_n, I, hi_n, R);
+                           (const float*)a, lo_n, I, hi_n, R, ld);
     return hipGetLastError();
 }
 
@@ -101,7 +105,7 @@ hipError_t launch_ttv(int fdt, const void* in, void* out, const void* a, int64_t
 // one block per row i; threads split (r, term) and reduce in LDS.
 // ---------------------------------------------------------------------------
 template <typename TC>
-__global__ __launch_bounds__(256) void k_grad(const TC* __restrict__ Z, TC* __restrict__ G, FacSet<TC> fs,
+__global__ __launch_bounds__(256) void k_grad(const TC* __restrict__ Z, int ld, TC* __restrict__ G, FacSet<TC> fs,
                                               int64_t lo_n, int64_t I, int64_t hi_n, int lo_first, int lo_count,
                                               int hi_first, int hi_count) {
     __shared__ double sred[256];
@@ -117,7 +121,7 @@ __global__ __launch_bounds__(256) void k_grad(const TC* __restrict__ Z, TC* __re
         for (int64_t t = g; t < nterms; t += groups) {
             const int64_t hi = t / lo_n;
             const int64_t lo = t - hi * lo_n;
-            const double z = (double)Z[(lo + lo_n * (i + I * hi)) * R + r];
+            const double z = (double)Z[(lo + lo_n * (i + I * hi)) * ld + r];
             acc += z * kr_entry_d(fs, lo_first, lo_count, lo, r) * kr_entry_d(fs, hi_first, hi_count, hi, r);
         }
     }
@@ -130,13 +134,13 @@ __global__ __launch_bounds__(256) void k_grad(const TC* __restrict__ Z, TC* __re
     }
 }
 
-hipError_t launch_grad(int fdt, const void* Z, void* G, const void* facset, int64_t lo_n, int64_t I,
+hipError_t launch_grad(int fdt, const void* Z, int ld, void* G, const void* facset, int64_t lo_n, int64_t I,
                        int64_t hi_n, int lo_first, int lo_count, int hi_first, int hi_count, hipStream_t s) {
     if (fdt == CPG_F64)
-        hipLaunchKernelGGL(k_grad<double>, dim3((unsigned)I), dim3(256), 0, s, (const double*)Z, (double*)G,
+        hipLaunchKernelGGL(k_grad<double>, dim3((unsigned)I), dim3(256), 0, s, (const double*)Z, ld, (double*)G,
                            *(const FacSet<double>*)facset, lo_n, I, hi_n, lo_first, lo_count, hi_first, hi_count);
     else
-        hipLaunchKernelGGL(k_grad<float>, dim3((unsigned)I), dim3(256), 0, s, (const float*)Z, (float*)G,
+        hipLaunchKernelGGL(k_grad<float>, dim3((unsigned)I), dim3(256), 0, s, (const float*)Z, ld, (float*)G,
                            *(const FacSet<float>*)facset, lo_n, I, hi_n, lo_first, lo_count, hi_first, hi_count);
     return hipGetLastError();
 }
@@ -347,8 +351,8 @@ hipError_t launch_norm2(int ydt, const void* Y, int64_t n, double* scratch, doub
 // <Y, Yhat> = sum_{j, r} P_R(j, r) * (A^(n*) (.) ... (.) A^(1))(j, r)
 // ---------------------------------------------------------------------------
 template <typename TC>
-__global__ __launch_bounds__(256) void k_inner_kr_stage1(const TC* __restrict__ PR, int64_t J, FacSet<TC> fs,
-                                                         int nstar, double* __restrict__ scratch) {
+__global__ __launch_bounds__(256) void k_inner_kr_stage1(const TC* __restrict__ PR, int ld, int64_t J,
+                                                         FacSet<TC> fs, int nstar, double* __restrict__ scratch) {
     __shared__ double sbuf[256];
     const int R = fs.R;
     const int64_t n = J * R;
@@ -356,19 +360,19 @@ __global__ __launch_bounds__(256) void k_inner_kr_stage1(const TC* __restrict__ 
     for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
         const int64_t j = e / R;
         const int r = (int)(e - j * R);
-        acc += (double)PR[e] * kr_entry_d(fs, 0, nstar, j, r);
+        acc += (double)PR[j * ld + r] * kr_entry_d(fs, 0, nstar, j, r);
     }
     const double t = block_sum_256(acc, sbuf);
     if (threadIdx.x == 0) scratch[blockIdx.x] = t;
 }
 
-hipError_t launch_inner_kr(int fdt, const void* PR, int64_t J, const void* facset, int nstar, double* scratch,
-                           double* out, hipStream_t s) {
+hipError_t launch_inner_kr(int fdt, const void* PR, int ld, int64_t J, const void* facset, int nstar,
+                           double* scratch, double* out, hipStream_t s) {
     if (fdt == CPG_F64)
-        hipLaunchKernelGGL(k_inner_kr_stage1<double>, dim3(kRedBlocks), dim3(256), 0, s, (const double*)PR, J,
+        hipLaunchKernelGGL(k_inner_kr_stage1<double>, dim3(kRedBlocks), dim3(256), 0, s, (const double*)PR, ld, J,
                            *(const FacSet<double>*)facset, nstar, scratch);
     else
-        hipLaunchKernelGGL(k_inner_kr_stage1<float>, dim3(kRedBlocks), dim3(256), 0, s, (const float*)PR, J,
+        hipLaunchKernelGGL(k_inner_kr_stage1<float>, dim3(kRedBlocks), dim3(256), 0, s, (const float*)PR, ld, J,
                            *(const FacSet<float>*)facset, nstar, scratch);
     hipLaunchKernelGGL(k_sum_stage2, dim3(1), dim3(256), 0, s, scratch, kRedBlocks, out);
     return hipGetLastError();

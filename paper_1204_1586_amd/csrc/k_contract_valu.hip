@@ -52,7 +52,7 @@ __device__ __forceinline__ TC kr_entry(const FacSet<TC>& fs, int first, int coun
 template <typename TY, typename TC, int RT, int JTB, bool DO_R, bool DO_L>
 __global__ __launch_bounds__(256) void k_contract_valu(const TY* __restrict__ Y, int64_t J, int64_t K,
                                                         FacSet<TC> fs, int nstar, int jtiles,
-                                                        int64_t ktiles, TC* __restrict__ PRpart,
+                                                        int64_t ktiles, int ld, TC* __restrict__ PRpart,
                                                         TC* __restrict__ PLpart) {
     constexpr int RC = RT < 16 ? RT : 16;   // rank chunk of the cross-wave reduction
     __shared__ TC sY[64][65];
@@ -147,9 +147,9 @@ __global__ __launch_bounds__(256) void k_contract_valu(const TY* __restrict__ Y,
 #pragma unroll
                     for (int q = 0; q < RC; ++q) {
                         const int r = rc + q;
-                        if (r < R) {
+                        if (r < ld) {
                             TC v = accL[r] + sRed[0][lane][q] + sRed[1][lane][q] + sRed[2][lane][q];
-                            PLpart[((int64_t)blockIdx.x * K + k) * R + r] = v;
+                            PLpart[((int64_t)blockIdx.x * K + k) * ld + r] = v;
                         }
                     }
                 }
@@ -174,10 +174,10 @@ __global__ __launch_bounds__(256) void k_contract_valu(const TY* __restrict__ Y,
 #pragma unroll
                         for (int q = 0; q < RC; ++q) {
                             const int r = rc + q;
-                            if (r < R) {
+                            if (r < ld) {
                                 TC v = accR[DO_R ? jt : 0][r] + sRed[0][lane][q] + sRed[1][lane][q] +
                                        sRed[2][lane][q];
-                                PRpart[((int64_t)blockIdx.y * J + j) * R + r] = v;
+                                PRpart[((int64_t)blockIdx.y * J + j) * ld + r] = v;
                             }
                         }
                     }
@@ -196,19 +196,19 @@ constexpr int valu_jtb() {
 
 template <typename TY, typename TC, int RT>
 static hipError_t dispatch_roles(const TY* Y, int64_t J, int64_t K, const FacSet<TC>& fs, int nstar,
-                                 const Tiling& t, int roles, TC* PRpart, TC* PLpart, hipStream_t s) {
+                                 const Tiling& t, int roles, int ld, TC* PRpart, TC* PLpart, hipStream_t s) {
     constexpr int JTB = valu_jtb<TC, RT>();
     if (t.jtb > JTB) return hipErrorInvalidValue;
     dim3 grid((unsigned)t.n_jr, (unsigned)t.n_kc);
     if (roles == 3)
         hipLaunchKernelGGL((k_contract_valu<TY, TC, RT, JTB, true, true>), grid, dim3(256), 0, s, Y, J, K, fs,
-                           nstar, t.jtb, t.ktb, PRpart, PLpart);
+                           nstar, t.jtb, t.ktb, ld, PRpart, PLpart);
     else if (roles == 1)
         hipLaunchKernelGGL((k_contract_valu<TY, TC, RT, JTB, true, false>), grid, dim3(256), 0, s, Y, J, K, fs,
-                           nstar, t.jtb, t.ktb, PRpart, PLpart);
+                           nstar, t.jtb, t.ktb, ld, PRpart, PLpart);
     else if (roles == 2)
         hipLaunchKernelGGL((k_contract_valu<TY, TC, RT, JTB, false, true>), grid, dim3(256), 0, s, Y, J, K, fs,
-                           nstar, t.jtb, t.ktb, PRpart, PLpart);
+                           nstar, t.jtb, t.ktb, ld, PRpart, PLpart);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -216,12 +216,12 @@ static hipError_t dispatch_roles(const TY* Y, int64_t J, int64_t K, const FacSet
 
 template <typename TY, typename TC>
 static hipError_t dispatch_rt(const TY* Y, int64_t J, int64_t K, const FacSet<TC>& fs, int nstar,
-                              const Tiling& t, int roles, TC* PRpart, TC* PLpart, hipStream_t s) {
+                              const Tiling& t, int roles, int ld, TC* PRpart, TC* PLpart, hipStream_t s) {
     switch (t.rt) {
-        case 4: return dispatch_roles<TY, TC, 4>(Y, J, K, fs, nstar, t, roles, PRpart, PLpart, s);
-        case 16: return dispatch_roles<TY, TC, 16>(Y, J, K, fs, nstar, t, roles, PRpart, PLpart, s);
-        case 32: return dispatch_roles<TY, TC, 32>(Y, J, K, fs, nstar, t, roles, PRpart, PLpart, s);
-        case 64: return dispatch_roles<TY, TC, 64>(Y, J, K, fs, nstar, t, roles, PRpart, PLpart, s);
+        case 4: return dispatch_roles<TY, TC, 4>(Y, J, K, fs, nstar, t, roles, ld, PRpart, PLpart, s);
+        case 16: return dispatch_roles<TY, TC, 16>(Y, J, K, fs, nstar, t, roles, ld, PRpart, PLpart, s);
+        case 32: return dispatch_roles<TY, TC, 32>(Y, J, K, fs, nstar, t, roles, ld, PRpart, PLpart, s);
+        case 64: return dispatch_roles<TY, TC, 64>(Y, J, K, fs, nstar, t, roles, ld, PRpart, PLpart, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -232,17 +232,17 @@ int valu_max_jtb(int fdt, int rt) {
 }
 
 hipError_t launch_contract_valu(int ydt, int fdt, const void* Y, int64_t J, int64_t K, const void* facset,
-                                int nstar, const Tiling& t, int roles, void* PRpart, void* PLpart,
+                                int nstar, const Tiling& t, int roles, int ld, void* PRpart, void* PLpart,
                                 hipStream_t stream) {
     if (fdt == CPG_F64 && ydt == CPG_F64)
         return dispatch_rt<double, double>((const double*)Y, J, K, *(const FacSet<double>*)facset, nstar, t,
-                                           roles, (double*)PRpart, (double*)PLpart, stream);
+                                           roles, ld, (double*)PRpart, (double*)PLpart, stream);
     if (fdt == CPG_F32 && ydt == CPG_F32)
-        return dispatch_rt<float, float>((const float*)Y, J, K, *(const FacSet<float>*)facset, nstar, t, roles,
+        return dispatch_rt<float, float>((const float*)Y, J, K, *(const FacSet<float>*)facset, nstar, t, roles, ld,
                                          (float*)PRpart, (float*)PLpart, stream);
     if (fdt == CPG_F32 && ydt == CPG_BF16)
         return dispatch_rt<uint16_t, float>((const uint16_t*)Y, J, K, *(const FacSet<float>*)facset, nstar, t,
-                                            roles, (float*)PRpart, (float*)PLpart, stream);
+                                            roles, ld, (float*)PRpart, (float*)PLpart, stream);
     return hipErrorInvalidValue;
 }
 

@@ -42,7 +42,23 @@ CASES = [
     ((33, 1, 65, 7), 1, "f32"),
     ((9, 70, 130), 33, "f32"),
     ((12, 10, 8, 6, 4), 32, "bf16"),
+    ((36, 20, 28, 33), 48, "f32"),
+    ((8, 600, 7), 64, "f32"),
+    ((12, 40, 36, 10), 20, "f32"),
 ]
+
+
+@pytest.mark.parametrize("dims,R", [((20, 30, 40, 50), 16), ((36, 20, 28, 33), 48), ((100, 77), 5),
+                                    ((8, 600, 7), 64), ((16, 16, 16, 16, 16), 32)])
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_both_contraction_kernels_match_oracle(dims, R, kernel):
+    """The vector-ALU and the MFMA contraction reach the oracle's gradients."""
+    print(f"[kernel {kernel}] dims={dims} R={R}", flush=True)
+    pr, A, G, _ = _all_modes(dims, R, "f32", kernel=kernel)
+    Y = exact_tensor(pr["y"], "f32", dims)
+    ref = O.cp_gradient_all(Y, exact_factors(A))
+    for n in range(len(dims)):
+        assert rel_fro(G[n], ref[n]) <= 1e-5, (n, rel_fro(G[n], ref[n]))
 
 
 @pytest.mark.parametrize("dims,R,storage", CASES)
@@ -107,6 +123,7 @@ def _als_setup(dims, R, storage, mode="native", seed=0, snr=25.0):
 
 @pytest.mark.parametrize("dims,R,storage,ftol", [((20, 20, 20), 3, "f64", 1e-10), ((11, 13, 9, 7), 5, "f64", 1e-10),
                                                  ((20, 30, 40, 50), 16, "f32", 2e-4),
+                                                 ((36, 20, 28, 33), 24, "f32", 2e-4),
                                                  ((5, 6, 3, 4, 2, 3, 5), 10, "f32", 2e-4)])
 def test_als_sweep_matches_oracle(dims, R, storage, ftol):
     print(f"[als] dims={dims} R={R} storage={storage}", flush=True)
