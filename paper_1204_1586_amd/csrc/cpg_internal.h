@@ -54,7 +54,7 @@ hipError_t launch_epilogue(int fdt, int R, const void* args, int nsides, hipStre
 
 // Tiling of one contraction pass over the J x K view Y_(1:n*).
 struct Tiling {
-    int kernel;        // 1 = generic vector ALU, 2 = MFMA
+    int kernel;        // 1 = generic vector ALU, 2 = float32 MFMA, 3 = bf16 MFMA
     int rt;            // rank tile (padded rank) used by the kernel
     int jtb;           // j-tiles (of 64 rows, or the MFMA kernel's row tile) per block
     int64_t ktb;       // k-tiles (of 64 columns) per block
@@ -79,6 +79,9 @@ struct MfmaOut {
     int ld;      // row stride (padded rank) of the partials
 };
 hipError_t launch_contract_mfma(int ydt, int mode, const void* Y, int64_t J, int64_t K,
+                                const FacSet<float>& fs, int nstar, const Tiling& t, int roles,
+                                const MfmaOut& out, hipStream_t stream);
+hipError_t launch_contract_bf16(int ydt, int mode, const void* Y, int64_t J, int64_t K,
                                 const FacSet<float>& fs, int nstar, const Tiling& t, int roles,
                                 const MfmaOut& out, hipStream_t stream);
 bool mfma_supported(int ydt, int fdt, int mode, int R);

@@ -86,9 +86,9 @@ static Tiling tile_valu(int64_t J, int64_t K, int R, int fdt, int roles) {
 
 // Tiling of one pass for the MFMA kernel: 256-row blocks, column chunks of
 // whole 32-column steps, about two blocks per compute unit.
-static Tiling tile_mfma(int64_t J, int64_t K, int R, int roles) {
+static Tiling tile_mfma(int64_t J, int64_t K, int R, int roles, int kernel) {
     Tiling t{};
-    t.kernel = 2;
+    t.kernel = kernel;
     t.rt = 16 * (int)cdiv(R, 16);
     t.jtb = 1;
     t.n_jr = cdiv(J, 256);
@@ -100,13 +100,17 @@ static Tiling tile_mfma(int64_t J, int64_t K, int R, int roles) {
     return t;
 }
 
-static bool use_mfma(const cpgrad_plan_s* p) {
-    if (p->kernel_opt == 1) return false;
-    return mfma_supported(p->ydt, p->fdt, p->mode, p->R) && (p->J % 4) == 0 && p->J < (int64_t(1) << 31);
+// 0 = generic kernel, 2 = float32 MFMA, 3 = bf16 MFMA (reduced-precision modes)
+static int mfma_kind(const cpgrad_plan_s* p) {
+    if (p->kernel_opt == 1 || p->J >= (int64_t(1) << 31)) return 0;
+    if (p->mode == CPG_MODE_NATIVE)
+        return (p->ydt == CPG_F32 && p->fdt == CPG_F32 && (p->J % 4) == 0) ? 2 : 0;
+    return (p->fdt == CPG_F32 && (p->ydt == CPG_F32 || p->ydt == CPG_BF16) && (p->J % 8) == 0) ? 3 : 0;
 }
 
 static Tiling tile_pass(const cpgrad_plan_s* p, int roles) {
-    if (use_mfma(p)) return tile_mfma(p->J, p->K, p->R, roles);
+    const int kind = mfma_kind(p);
+    if (kind) return tile_mfma(p->J, p->K, p->R, roles, kind);
     return tile_valu(p->J, p->K, p->R, p->fdt, roles);
 }
 
@@ -212,8 +216,10 @@ static AnyFacSet facsets(const cpgrad_plan_s* p, const void* const* A) {
 static hipError_t launch_contract(cpgrad_plan_s* p, const void* Y, const AnyFacSet& fs, const Tiling& t,
                                   int roles) {
     if (t.n_kc > 65535) return hipErrorInvalidConfiguration;
-    if (t.kernel == 2) {
+    if (t.kernel == 2 || t.kernel == 3) {
         MfmaOut o{(float*)p->PRpart, (float*)p->PLpart, p->ld};
+        if (t.kernel == 3)
+            return launch_contract_bf16(p->ydt, p->mode, Y, p->J, p->K, fs.f, p->nstar, t, roles, o, p->stream);
         return launch_contract_mfma(p->ydt, p->mode, Y, p->J, p->K, fs.f, p->nstar, t, roles, o, p->stream);
     }
     return launch_contract_valu(p->ydt, p->fdt, Y, p->J, p->K, fs.ptr(p->fdt), p->nstar, t, roles, p->ld,

@@ -1,0 +1,111 @@
+"""Reduced-precision form of the big contraction (bf16 matrix cores, float32
+accumulation, optional same-pass refinement) against the float64 oracle.
+
+The paper fixes no precision for this form, so parity is bounded rather than
+exact: every entry must satisfy |G_gpu - G_ref| <= c * Gabs, where Gabs is the
+same CP gradient computed by the oracle with |Y| and |A^(k)| (the sum of the
+magnitudes of the terms) and c is the rounding bound of the mode:
+  bf16          : c = 2 u + u^2 + 2e-5,   u = 2^-8 (operands rounded once each)
+  bf16 refined  : c = 4 u^2 + 2e-5        (hi/lo split leaves an O(u^2) residual)
+the 2e-5 covering float32 accumulation and the float32 chain steps.  The
+per-mode relative errors are printed (the error report of this form)."""
+import numpy as np
+import pytest
+import torch
+
+import cpgen
+import oracle as O
+from gpu_util import exact_factors, exact_tensor, rel_fro, to_device_factors, to_device_y
+
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -8
+BOUND = {"bf16": 2 * U + U * U + 2e-5, "bf16_refined": 4 * U * U + 2e-5}
+
+
+def _run(pr, storage, mode):
+    import paper_1204_1586_amd as P
+    dims, R = pr["dims"], pr["R"]
+    Y = to_device_y(pr["y"], storage)
+    A = to_device_factors(pr["init"], "f32")
+    G = [torch.empty_like(M) for M in A]
+    plan = P.cpgrad_plan(dims, R, storage, "f32", mode)
+    P.cpgrad_all_modes(plan, Y, A, G)
+    torch.cuda.synchronize()
+    return A, [g.cpu().double().numpy() for g in G]
+
+
+@pytest.mark.parametrize("dims,R,storage,mode", [
+    ((12, 10, 8, 6, 4), 32, "bf16", "bf16_refined"),
+    ((12, 10, 8, 6, 4), 32, "bf16", "bf16"),
+    ((6, 5, 4, 6, 5, 4, 6), 10, "f32", "bf16_refined"),
+    ((6, 5, 4, 6, 5, 4, 6), 10, "f32", "bf16"),
+    ((40, 24, 30, 33), 20, "f32", "bf16_refined"),
+    ((16, 16, 16, 16), 48, "bf16", "bf16_refined"),
+])
+def test_bf16_contraction_within_rounding_bound(dims, R, storage, mode):
+    print(f"[bf16] dims={dims} R={R} storage={storage} mode={mode}", flush=True)
+    pr = cpgen.make_problem("cp7d_10_r10_f32", rep=2000, dims=dims, rank=R, storage=storage)
+    A, G = _run(pr, storage, mode)
+    Y = exact_tensor(pr["y"], storage, dims)
+    Ax = exact_factors(A)
+    ref = O.cp_gradient_all(Y, Ax)
+    gabs = O.cp_gradient_all(np.abs(Y), [np.abs(M) for M in Ax])
+    errs = []
+    for n in range(len(dims)):
+        err = np.abs(G[n] - ref[n])
+        assert np.all(err <= BOUND[mode] * gabs[n] + 1e-30), (n, float(np.max(err / (gabs[n] + 1e-300))))
+        errs.append(rel_fro(G[n], ref[n]))
+    print("  per-mode relative error:", " ".join(f"{e:.2e}" for e in errs), flush=True)
+    if mode == "bf16_refined":
+        assert max(errs) < 1e-4
+
+
+def test_bf16_refined_is_more_accurate_than_plain_bf16():
+    dims, R = (6, 5, 4, 6, 5, 4, 6), 10
+    pr = cpgen.make_problem("cp7d_10_r10_f32", rep=2001, dims=dims, rank=R, storage="f32")
+    Y = exact_tensor(pr["y"], "f32", dims)
+    A, Gp = _run(pr, "f32", "bf16")
+    _, Gr = _run(pr, "f32", "bf16_refined")
+    ref = O.cp_gradient_all(Y, exact_factors(A))
+    ep = max(rel_fro(Gp[n], ref[n]) for n in range(7))
+    er = max(rel_fro(Gr[n], ref[n]) for n in range(7))
+    print(f"  bf16 {ep:.2e}  refined {er:.2e}", flush=True)
+    assert er < ep / 20
+
+
+def test_full_size_7d_bf16_refined_sampled():
+    """10^7 tensor, rank 10, float32 storage: sampled entries of every mode's
+    gradient against the oracle's element-wise definition (eq. 3.2)."""
+    w = cpgen.WORKLOADS["cp7d_10_r10_f32"]
+    pr = cpgen.make_problem(w, rep=0)
+    A, G = _run(pr, "f32", "bf16_refined")
+    Y = exact_tensor(pr["y"], "f32", pr["dims"])
+    Ax = exact_factors(A)
+    Aabs = [np.abs(M) for M in Ax]
+    g = np.random.default_rng(5)
+    for n in range(7):
+        for _ in range(3):
+            i, r = int(g.integers(10)), int(g.integers(10))
+            ref = O.gradient_entry(Y, Ax, n, i, r)
+            gab = O.gradient_entry(np.abs(Y), Aabs, n, i, r)
+            assert abs(G[n][i, r] - ref) <= BOUND["bf16_refined"] * gab, (n, i, r)
+
+
+def test_als_sweep_in_bf16_refined_mode():
+    """The ALS sweep runs unchanged on the refined contraction: one sweep from
+    the same state lands within the rounding bound's reach of the oracle's."""
+    import paper_1204_1586_amd as P
+    dims, R = (12, 10, 8, 6, 4), 8
+    pr = cpgen.make_problem("cp5d_48_r32_bf16", rep=2002, dims=dims, rank=R, storage="bf16")
+    Y = to_device_y(pr["y"], "bf16")
+    A = to_device_factors(pr["init"], "f32")
+    plan = P.cpgrad_plan(dims, R, "bf16", "f32", "bf16_refined")
+    P.cpgrad_bind(plan, Y)
+    A0 = exact_factors(A)
+    cost, fit = P.cpals_step(plan, Y, A)
+    Yx = exact_tensor(pr["y"], "bf16", dims)
+    A_ref, D_ref, fit_ref = O.als_sweep(Yx, A0)
+    for n in range(len(dims)):
+        assert rel_fro(exact_factors(A)[n], A_ref[n]) < 1e-3
+    assert abs(fit - fit_ref) < 1e-4
