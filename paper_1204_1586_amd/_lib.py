@@ -27,9 +27,13 @@ DTYPES = {"f64": CPG_F64, "f32": CPG_F32, "bf16": CPG_BF16}
 MODES = {"native": CPG_MODE_NATIVE, "bf16": CPG_MODE_BF16, "bf16_refined": CPG_MODE_BF16_REFINED}
 TORCH_DTYPE = {CPG_F64: torch.float64, CPG_F32: torch.float32, CPG_BF16: torch.bfloat16}
 
-EXPORTS = ["cpgrad_plan", "cpgrad_plan_info", "cpgrad_query", "cpgrad_set_option", "cpgrad_profile_read", "cpgrad_bind", "cpgrad_all_modes",
-           "cpals_step", "cp_fit", "cpgrad_last_fit", "cpgrad_destroy", "cpgrad_status_string",
-           "cpgrad_version"]
+EXPORTS = ["cpgrad_plan", "cpgrad_plan_info", "cpgrad_query", "cpgrad_set_option", "cpgrad_profile_read",
+           "cpgrad_bind", "cpgrad_all_modes", "cpals_step", "cp_fit", "cpgrad_last_fit", "cpgrad_destroy",
+           "cpgrad_status_string", "cpgrad_version",
+           "cpmlp_create", "cpmlp_num_params", "cpmlp_set_params", "cpmlp_get_params", "cpmlp_forward",
+           "cpmlp_gradients", "cpmlp_train_step", "cpmlp_destroy", "cpals_features", "cp_fit_extrapolated",
+           "cpals_learned_step"]
+NFEAT = 12
 
 
 class CpgError(RuntimeError):
@@ -61,6 +65,21 @@ def _load():
         "cpgrad_destroy": (ctypes.c_int, [vp]),
         "cpgrad_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "cpgrad_version": (ctypes.c_char_p, []),
+        "cpmlp_create": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.c_float, vp]),
+        "cpmlp_num_params": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int64)]),
+        "cpmlp_set_params": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_int64]),
+        "cpmlp_get_params": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_int64]),
+        "cpmlp_forward": (ctypes.c_int, [vp, vp, ctypes.c_int, vp]),
+        "cpmlp_gradients": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, vp, dp]),
+        "cpmlp_train_step": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, ctypes.c_float, dp]),
+        "cpmlp_destroy": (ctypes.c_int, [vp]),
+        "cpals_features": (ctypes.c_int, [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), dp, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_float, ctypes.c_int, vp]),
+        "cp_fit_extrapolated": (ctypes.c_int, [vp, vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_double, dp,
+                                               dp]),
+        "cpals_learned_step": (ctypes.c_int, [vp, vp, vp, ctypes.POINTER(vp), dp, ctypes.c_int, ctypes.c_int,
+                                              ctypes.c_float, ctypes.c_int, dp, dp, ctypes.POINTER(ctypes.c_int),
+                                              ctypes.POINTER(ctypes.c_float)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -233,3 +252,123 @@ def cpgrad_destroy(plan):
 
 def cpgrad_version():
     return LIB.cpgrad_version().decode()
+
+
+# ---------------------------------------------------------------------------
+# learned extrapolation step (include/cpmlp.h)
+# ---------------------------------------------------------------------------
+
+class Mlp:
+    """Owns a cpmlp_t (the step-size network)."""
+
+    def __init__(self, handle, n_in, n_hidden, sigma_max, stream):
+        self.handle = handle
+        self.n_in, self.n_hidden, self.sigma_max = n_in, n_hidden, sigma_max
+        self.stream = stream
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            LIB.cpmlp_destroy(h)
+            self.handle = None
+
+
+def cpmlp_create(n_in, n_hidden, sigma_max, stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    h = ctypes.c_void_p()
+    _check(LIB.cpmlp_create(ctypes.byref(h), int(n_in), int(n_hidden), float(sigma_max),
+                            ctypes.c_void_p(stream.cuda_stream)), "cpmlp_create")
+    return Mlp(h, int(n_in), int(n_hidden), float(sigma_max), stream)
+
+
+def cpmlp_num_params(m):
+    n = ctypes.c_int64()
+    _check(LIB.cpmlp_num_params(m.handle, ctypes.byref(n)), "cpmlp_num_params")
+    return n.value
+
+
+def cpmlp_set_params(m, params):
+    import numpy as np
+    a = np.ascontiguousarray(params, dtype=np.float32)
+    _check(LIB.cpmlp_set_params(m.handle, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), a.size),
+           "cpmlp_set_params")
+
+
+def cpmlp_get_params(m):
+    import numpy as np
+    a = np.empty(cpmlp_num_params(m), dtype=np.float32)
+    _check(LIB.cpmlp_get_params(m.handle, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), a.size),
+           "cpmlp_get_params")
+    return a
+
+
+def _f32(t, shape=None):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous() and t.dtype == torch.float32):
+        raise ValueError("expected a contiguous float32 CUDA tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"expected shape {shape}, got {tuple(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def cpmlp_forward(m, X, sigma):
+    B = X.shape[0]
+    _check(LIB.cpmlp_forward(m.handle, _f32(X, (B, m.n_in)), B, _f32(sigma, (B,))), "cpmlp_forward")
+
+
+def cpmlp_gradients(m, X, target, grad):
+    B = X.shape[0]
+    loss = ctypes.c_double()
+    _check(LIB.cpmlp_gradients(m.handle, _f32(X, (B, m.n_in)), _f32(target, (B,)), B,
+                               _f32(grad, (cpmlp_num_params(m),)), ctypes.byref(loss)), "cpmlp_gradients")
+    return loss.value
+
+
+def cpmlp_train_step(m, X, target, lr):
+    B = X.shape[0]
+    loss = ctypes.c_double()
+    _check(LIB.cpmlp_train_step(m.handle, _f32(X, (B, m.n_in)), _f32(target, (B,)), B, float(lr),
+                                ctypes.byref(loss)), "cpmlp_train_step")
+    return loss.value
+
+
+def cpmlp_destroy(m):
+    if m.handle:
+        _check(LIB.cpmlp_destroy(m.handle), "cpmlp_destroy")
+        m.handle = None
+
+
+def _costs(costs):
+    arr = (ctypes.c_double * max(1, len(costs)))(*[float(c) for c in costs])
+    return arr, len(costs)
+
+
+def cpals_features(plan, A, A_start, costs, iteration, last_sigma, last_accept, feat):
+    _check_factors(plan, A)
+    _check_factors(plan, A_start, "A_start")
+    arr, nc = _costs(costs)
+    _check(LIB.cpals_features(plan.handle, _ptrs(A), _ptrs(A_start), arr, nc, int(iteration), float(last_sigma),
+                              int(last_accept), _f32(feat, (NFEAT,))), "cpals_features")
+
+
+def cp_fit_extrapolated(plan, Y, A, A_start, sigma):
+    _check_y(plan, Y)
+    _check_factors(plan, A)
+    _check_factors(plan, A_start, "A_start")
+    c, f = ctypes.c_double(), ctypes.c_double()
+    _check(LIB.cp_fit_extrapolated(plan.handle, ctypes.c_void_p(Y.data_ptr()), _ptrs(A), _ptrs(A_start),
+                                   float(sigma), ctypes.byref(c), ctypes.byref(f)), "cp_fit_extrapolated")
+    return c.value, f.value
+
+
+def cpals_learned_step(plan, mlp, Y, A, costs, iteration, last_sigma, last_accept):
+    """One learned-extrapolation ALS step; returns (cost, fit, accepted, sigma)."""
+    _check_y(plan, Y)
+    _check_factors(plan, A)
+    arr, nc = _costs(costs)
+    c, f = ctypes.c_double(), ctypes.c_double()
+    acc, sg = ctypes.c_int(), ctypes.c_float()
+    _check(LIB.cpals_learned_step(plan.handle, mlp.handle, ctypes.c_void_p(Y.data_ptr()), _ptrs(A), arr, nc,
+                                  int(iteration), float(last_sigma), int(last_accept), ctypes.byref(c),
+                                  ctypes.byref(f), ctypes.byref(acc), ctypes.byref(sg)), "cpals_learned_step")
+    return c.value, f.value, acc.value, sg.value

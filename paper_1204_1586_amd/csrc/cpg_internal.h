@@ -8,6 +8,8 @@
 
 #include "cpgrad.h"
 
+struct cpmlp_s;
+
 namespace cpg {
 
 // Factor set handed to kernels by value: every mode's extent and factor
@@ -120,9 +122,22 @@ hipError_t launch_inner_kr(int fdt, const void* PR, int ld, int64_t J, const voi
 
 // cost and fit in float64.  If G is non-null, inner = sum G .* A (I x R);
 // otherwise inner is read from *inner_in.  scal: [0]=||Y||^2, writes [2]=cost,
-// [3]=fit; flags[0] |= 2 if non-finite.
+// [3]=fit (or [out_slot], [out_slot+1]); flags[0] |= 2 if non-finite.
 hipError_t launch_cost_fit(int fdt, const void* G, const void* A, int64_t I, int R,
                            const double* inner_in, const double* grams, int N, double* scal,
-                           int* flags, hipStream_t stream);
+                           int* flags, hipStream_t stream, int out_slot = 2);
+
+// learned extrapolation step (k_learn.hip); factor sets are FacSet<T> of the plan's type
+hipError_t launch_copy_factors(int fdt, const void* dst, const void* src, hipStream_t stream);
+hipError_t launch_extrapolate(int fdt, const void* out, const void* A, const void* As, const float* sigma_dev,
+                              double sigma_val, hipStream_t stream);
+hipError_t launch_accept(int fdt, const void* A, const void* Aext, double* scal, int* accepted,
+                         hipStream_t stream);
+hipError_t launch_features(int fdt, const void* A, const void* As, const void* Dp, const double* costs, int ncost,
+                           const double* cur_cost_dev, int iteration, float last_sigma, int last_accept,
+                           int have_prev, float* feat, hipStream_t stream);
+// the step-size network (k_mlp.hip)
+hipError_t launch_mlp_forward(struct ::cpmlp_s* m, const float* X, int batch, float* sigma, hipStream_t stream);
+int mlp_num_inputs(struct ::cpmlp_s* m);
 
 }  // namespace cpg

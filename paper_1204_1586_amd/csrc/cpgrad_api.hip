@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "cpg_internal.h"
+#include "cpmlp.h"
 
 using namespace cpg;
 
@@ -41,6 +42,17 @@ struct cpgrad_plan_s {
     int* flags = nullptr;
     double* host = nullptr;   // pinned readback: scal[0..7], flags
     const void* bound = nullptr;
+    // learned extrapolation step: start / previous-update / extrapolated factors, features, sigma
+    char* lws = nullptr;
+    size_t lws_bytes = 0;
+    int64_t fac_off[CPG_MAX_MODES] = {0};   // element offset of each mode in a factor set
+    void* l_start = nullptr;
+    void* l_dprev = nullptr;
+    void* l_ext = nullptr;
+    float* l_feat = nullptr;
+    float* l_sigma = nullptr;
+    int* l_accept = nullptr;
+    int have_prev = 0;
     // optional HIP-event timing of the big contraction launches
     int profile = 0;
     std::vector<hipEvent_t> ev_start, ev_stop;
@@ -513,6 +525,91 @@ __global__ void k_zero_flags(int* f) {
     if (threadIdx.x < 16) f[threadIdx.x] = 0;
 }
 
+// One ALS sweep enqueued on the plan's stream (no host wait): cost and fit end
+// in scal[2], scal[3], failures in flags.
+static int als_sweep_core(cpgrad_plan_s* p, const void* Y, void* const* A) {
+    const AnyFacSet fs = facsets(p, (const void* const*)A);
+    const bool epi = epilogue_fits(p);
+    if (!epi) {
+        hipLaunchKernelGGL(k_zero_flags, dim3(1), dim3(64), 0, p->stream, p->flags);
+        CPG_TRY(hipGetLastError());
+        CPG_TRY(launch_grams(p->fdt, fs.ptr(p->fdt), p->grams, p->stream));
+    }
+    // pass 1 over Y: P_R with the current A^(n*+1..N), then modes n*, ..., 1
+    CPG_TRY(run_contract(p, Y, fs, p->t_right, 1));
+    int st = finish_partials(p, p->t_right, 1);
+    if (st) return st;
+    if (epi)
+        st = p->fdt == CPG_F64 ? run_side<double>(p, fs.d, 0, A, nullptr, true, true, false)
+                               : run_side<float>(p, fs.f, 0, A, nullptr, true, true, false);
+    else
+        st = right_chain(p, fs, A, nullptr, true);
+    if (st) return st;
+    // pass 2 over Y: P_L with the updated A^(1..n*), then modes n*+1, ..., N and the cost
+    CPG_TRY(run_contract(p, Y, fs, p->t_left, 2));
+    st = finish_partials(p, p->t_left, 2);
+    if (st) return st;
+    if (epi) {
+        st = p->fdt == CPG_F64 ? run_side<double>(p, fs.d, 1, A, nullptr, true, false, true)
+                               : run_side<float>(p, fs.f, 1, A, nullptr, true, false, true);
+        if (st) return st;
+    } else {
+        st = left_chain(p, fs, A, nullptr, true);
+        if (st) return st;
+        // cost of eq. 2.12: Gtmp holds G^(N) (taken before the A^(N) update)
+        CPG_TRY(launch_cost_fit(p->fdt, p->Gtmp, A[p->N - 1], p->dims[p->N - 1], p->R, nullptr, p->grams, p->N,
+                                p->scal, p->flags, p->stream));
+    }
+    return CPG_OK;
+}
+
+// Cost of eq. 2.12 of the model given by the factor set `fs` against Y, into
+// scal[slot], scal[slot+1] (no host wait).  Recomputes every Gram.
+static int fit_core(cpgrad_plan_s* p, const void* Y, const AnyFacSet& fs, int slot) {
+    CPG_TRY(launch_grams(p->fdt, fs.ptr(p->fdt), p->grams, p->stream));
+    CPG_TRY(run_contract(p, Y, fs, p->t_right, 1));
+    int st = finish_partials(p, p->t_right, 1);
+    if (st) return st;
+    CPG_TRY(launch_inner_kr(p->fdt, p->PR, p->ld, p->J, fs.ptr(p->fdt), p->nstar, p->red, p->scal + 6,
+                            p->stream));
+    CPG_TRY(launch_cost_fit(p->fdt, nullptr, nullptr, 0, p->R, p->scal + 6, p->grams, p->N, p->scal, p->flags,
+                            p->stream, slot));
+    return CPG_OK;
+}
+
+// Scratch of the learned step: three factor sets of the plan's type, the
+// features, sigma and the accept flag.
+static int ensure_learn(cpgrad_plan_s* p) {
+    if (p->lws) return CPG_OK;
+    int64_t tot = 0;
+    for (int n = 0; n < p->N; ++n) {
+        p->fac_off[n] = tot;
+        tot += ((p->dims[n] * p->R + 63) / 64) * 64;
+    }
+    const size_t fb = (size_t)tot * p->acc;
+    const size_t bytes = 3 * fb + 256;
+    if (hipMalloc((void**)&p->lws, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        p->lws = nullptr;
+        return CPG_ERR_NOMEM;
+    }
+    p->lws_bytes = bytes;
+    p->l_start = p->lws;
+    p->l_dprev = p->lws + fb;
+    p->l_ext = p->lws + 2 * fb;
+    p->l_feat = (float*)(p->lws + 3 * fb);
+    p->l_sigma = p->l_feat + 32;
+    p->l_accept = (int*)(p->l_sigma + 4);
+    p->have_prev = 0;
+    return hipMemsetAsync(p->lws, 0, bytes, p->stream) == hipSuccess ? CPG_OK : CPG_ERR_HIP;
+}
+
+static AnyFacSet plan_facset(const cpgrad_plan_s* p, void* base) {
+    const void* ptrs[CPG_MAX_MODES];
+    for (int n = 0; n < p->N; ++n) ptrs[n] = (const char*)base + p->fac_off[n] * p->acc;
+    return facsets(p, ptrs);
+}
+
 extern "C" {
 
 const char* cpgrad_version(void) { return "cpgrad 0.1 (gfx950)"; }
@@ -652,6 +749,7 @@ int cpgrad_bind(cpgrad_plan_t p, const void* Y) {
     if (((uintptr_t)Y & 15) != 0) return CPG_ERR_INVALID;
     if (launch_norm2(p->ydt, Y, p->numel, p->red, p->scal, p->stream) != hipSuccess) return CPG_ERR_HIP;
     p->bound = Y;
+    p->have_prev = 0;
     return CPG_OK;
 }
 
@@ -678,38 +776,8 @@ int cpals_step(cpgrad_plan_t p, const void* Y, void* const* A, double* cost_out,
     if (Y != p->bound) return CPG_ERR_INVALID;
     for (int n = 0; n < p->N; ++n)
         if (!A[n]) return CPG_ERR_INVALID;
-    const AnyFacSet fs = facsets(p, (const void* const*)A);
-    const bool epi = epilogue_fits(p);
-    if (!epi) {
-        hipLaunchKernelGGL(k_zero_flags, dim3(1), dim3(64), 0, p->stream, p->flags);
-        CPG_TRY(hipGetLastError());
-        CPG_TRY(launch_grams(p->fdt, fs.ptr(p->fdt), p->grams, p->stream));
-    }
-    // pass 1 over Y: P_R with the current A^(n*+1..N), then modes n*, ..., 1
-    CPG_TRY(run_contract(p, Y, fs, p->t_right, 1));
-    int st = finish_partials(p, p->t_right, 1);
+    const int st = als_sweep_core(p, Y, A);
     if (st) return st;
-    if (epi)
-        st = p->fdt == CPG_F64 ? run_side<double>(p, fs.d, 0, A, nullptr, true, true, false)
-                               : run_side<float>(p, fs.f, 0, A, nullptr, true, true, false);
-    else
-        st = right_chain(p, fs, A, nullptr, true);
-    if (st) return st;
-    // pass 2 over Y: P_L with the updated A^(1..n*), then modes n*+1, ..., N and the cost
-    CPG_TRY(run_contract(p, Y, fs, p->t_left, 2));
-    st = finish_partials(p, p->t_left, 2);
-    if (st) return st;
-    if (epi) {
-        st = p->fdt == CPG_F64 ? run_side<double>(p, fs.d, 1, A, nullptr, true, false, true)
-                               : run_side<float>(p, fs.f, 1, A, nullptr, true, false, true);
-        if (st) return st;
-    } else {
-        st = left_chain(p, fs, A, nullptr, true);
-        if (st) return st;
-        // cost of eq. 2.12: Gtmp holds G^(N) (taken before the A^(N) update)
-        CPG_TRY(launch_cost_fit(p->fdt, p->Gtmp, A[p->N - 1], p->dims[p->N - 1], p->R, nullptr, p->grams, p->N,
-                                p->scal, p->flags, p->stream));
-    }
     if (!cost_out && !fit_out) return CPG_OK;
     return readback(p, cost_out, fit_out);
 }
@@ -722,15 +790,75 @@ int cp_fit(cpgrad_plan_t p, const void* Y, const void* const* A, double* cost_ou
     const AnyFacSet fs = facsets(p, A);
     hipLaunchKernelGGL(k_zero_flags, dim3(1), dim3(64), 0, p->stream, p->flags);
     CPG_TRY(hipGetLastError());
-    CPG_TRY(launch_grams(p->fdt, fs.ptr(p->fdt), p->grams, p->stream));
-    CPG_TRY(run_contract(p, Y, fs, p->t_right, 1));
-    int st = finish_partials(p, p->t_right, 1);
+    const int st = fit_core(p, Y, fs, 2);
     if (st) return st;
-    CPG_TRY(launch_inner_kr(p->fdt, p->PR, p->ld, p->J, fs.ptr(p->fdt), p->nstar, p->red, p->scal + 6,
-                            p->stream));
-    CPG_TRY(launch_cost_fit(p->fdt, nullptr, nullptr, 0, p->R, p->scal + 6, p->grams, p->N, p->scal, p->flags,
-                            p->stream));
     return readback(p, cost_out, fit_out);
+}
+
+int cpals_features(cpgrad_plan_t p, const void* const* A, const void* const* A_start, const double* costs,
+                   int ncost, int iteration, float last_sigma, int last_accept, float* feat) {
+    if (!p || !A || !A_start || !feat || ncost < 0 || (ncost > 0 && !costs)) return CPG_ERR_INVALID;
+    for (int n = 0; n < p->N; ++n)
+        if (!A[n] || !A_start[n]) return CPG_ERR_INVALID;
+    int st = ensure_learn(p);
+    if (st) return st;
+    const AnyFacSet a = facsets(p, A), s0 = facsets(p, A_start), d = plan_facset(p, p->l_dprev);
+    CPG_TRY(launch_features(p->fdt, a.ptr(p->fdt), s0.ptr(p->fdt), d.ptr(p->fdt), costs, ncost, nullptr, iteration,
+                            last_sigma, last_accept, p->have_prev, feat, p->stream));
+    p->have_prev = 1;
+    return CPG_OK;
+}
+
+int cp_fit_extrapolated(cpgrad_plan_t p, const void* Y, const void* const* A, const void* const* A_start,
+                        double sigma, double* cost_out, double* fit_out) {
+    if (!p || !Y || !A || !A_start) return CPG_ERR_INVALID;
+    if (Y != p->bound) return CPG_ERR_INVALID;
+    for (int n = 0; n < p->N; ++n)
+        if (!A[n] || !A_start[n]) return CPG_ERR_INVALID;
+    int st = ensure_learn(p);
+    if (st) return st;
+    const AnyFacSet a = facsets(p, A), s0 = facsets(p, A_start), e = plan_facset(p, p->l_ext);
+    CPG_TRY(launch_extrapolate(p->fdt, e.ptr(p->fdt), a.ptr(p->fdt), s0.ptr(p->fdt), nullptr, sigma, p->stream));
+    hipLaunchKernelGGL(k_zero_flags, dim3(1), dim3(64), 0, p->stream, p->flags);
+    CPG_TRY(hipGetLastError());
+    st = fit_core(p, Y, e, 2);
+    if (st) return st;
+    return readback(p, cost_out, fit_out);
+}
+
+int cpals_learned_step(cpgrad_plan_t p, cpmlp_t m, const void* Y, void* const* A, const double* costs, int ncost,
+                       int iteration, float last_sigma, int last_accept, double* cost_out, double* fit_out,
+                       int* accepted, float* sigma_out) {
+    if (!p || !m || !Y || !A || ncost < 0 || (ncost > 0 && !costs)) return CPG_ERR_INVALID;
+    if (Y != p->bound || mlp_num_inputs(m) != CPG_NFEAT) return CPG_ERR_INVALID;
+    for (int n = 0; n < p->N; ++n)
+        if (!A[n]) return CPG_ERR_INVALID;
+    int st = ensure_learn(p);
+    if (st) return st;
+    const AnyFacSet a = facsets(p, (const void* const*)A), s0 = plan_facset(p, p->l_start),
+                    d = plan_facset(p, p->l_dprev), e = plan_facset(p, p->l_ext);
+    CPG_TRY(launch_copy_factors(p->fdt, s0.ptr(p->fdt), a.ptr(p->fdt), p->stream));
+    st = als_sweep_core(p, Y, A);   // A <- plain ALS sweep, cost in scal[2]
+    if (st) return st;
+    CPG_TRY(launch_features(p->fdt, a.ptr(p->fdt), s0.ptr(p->fdt), d.ptr(p->fdt), costs, ncost, p->scal + 2,
+                            iteration, last_sigma, last_accept, p->have_prev, p->l_feat, p->stream));
+    p->have_prev = 1;
+    CPG_TRY(launch_mlp_forward(m, p->l_feat, 1, p->l_sigma, p->stream));
+    CPG_TRY(launch_extrapolate(p->fdt, e.ptr(p->fdt), a.ptr(p->fdt), s0.ptr(p->fdt), p->l_sigma, 0.0, p->stream));
+    st = fit_core(p, Y, e, 8);      // exact cost of the extrapolated factors in scal[8]
+    if (st) return st;
+    CPG_TRY(launch_accept(p->fdt, a.ptr(p->fdt), e.ptr(p->fdt), p->scal, p->l_accept, p->stream));
+    if (hipMemcpyAsync(p->host + 10, p->l_sigma, sizeof(float), hipMemcpyDeviceToHost, p->stream) != hipSuccess ||
+        hipMemcpyAsync(p->host + 11, p->l_accept, sizeof(int), hipMemcpyDeviceToHost, p->stream) != hipSuccess)
+        return CPG_ERR_HIP;
+    st = readback(p, cost_out, fit_out);   // waits for the stream
+    float sg = 0.f;
+    int acc = 0;
+    std::memcpy(&sg, p->host + 10, sizeof(float));
+    std::memcpy(&acc, p->host + 11, sizeof(int));
+    if (accepted) *accepted = acc;
+    if (sigma_out) *sigma_out = sg;
+    return st;
 }
 
 int cpgrad_last_fit(cpgrad_plan_t p, double* cost_out, double* fit_out) {
@@ -743,6 +871,7 @@ int cpgrad_destroy(cpgrad_plan_t p) {
     if (p->stream) (void)hipStreamSynchronize(p->stream);
     else (void)hipDeviceSynchronize();
     release(p);
+    if (p->lws) (void)hipFree(p->lws);
     if (p->host) (void)hipHostFree(p->host);
     for (size_t i = 0; i < p->ev_start.size(); ++i) {
         (void)hipEventDestroy(p->ev_start[i]);

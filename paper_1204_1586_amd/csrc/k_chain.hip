@@ -385,7 +385,7 @@ template <typename TC>
 __global__ __launch_bounds__(256) void k_cost_fit(const TC* __restrict__ G, const TC* __restrict__ A, int64_t I,
                                                   int R, const double* __restrict__ inner_in,
                                                   const double* __restrict__ grams, int N, double* __restrict__ scal,
-                                                  int* __restrict__ flags) {
+                                                  int* __restrict__ flags, int out) {
     __shared__ double sbuf[256];
     double acc = 0.0;
     if (G != nullptr)
@@ -402,22 +402,24 @@ __global__ __launch_bounds__(256) void k_cost_fit(const TC* __restrict__ G, cons
         const double y2 = scal[0];
         const double D = y2 - 2.0 * inner + nrm;
         const double fit = 1.0 - sqrt(D > 0.0 ? D : 0.0) / sqrt(y2);
-        scal[2] = D;
-        scal[3] = fit;
-        scal[4] = inner;
-        scal[5] = nrm;
-        if (!isfinite(D) || !isfinite(fit)) atomicOr(flags, 2);
+        scal[out] = D;
+        scal[out + 1] = fit;
+        if (out == 2) {
+            scal[4] = inner;
+            scal[5] = nrm;
+        }
+        if (out == 2 && (!isfinite(D) || !isfinite(fit))) atomicOr(flags, 2);
     }
 }
 
 hipError_t launch_cost_fit(int fdt, const void* G, const void* A, int64_t I, int R, const double* inner_in,
-                           const double* grams, int N, double* scal, int* flags, hipStream_t s) {
+                           const double* grams, int N, double* scal, int* flags, hipStream_t s, int out_slot) {
     if (fdt == CPG_F64)
         hipLaunchKernelGGL(k_cost_fit<double>, dim3(1), dim3(256), 0, s, (const double*)G, (const double*)A, I, R,
-                           inner_in, grams, N, scal, flags);
+                           inner_in, grams, N, scal, flags, out_slot);
     else
         hipLaunchKernelGGL(k_cost_fit<float>, dim3(1), dim3(256), 0, s, (const float*)G, (const float*)A, I, R,
-                           inner_in, grams, N, scal, flags);
+                           inner_in, grams, N, scal, flags, out_slot);
     return hipGetLastError();
 }
 

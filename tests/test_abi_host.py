@@ -12,11 +12,11 @@ import pytest
 import oracle as O
 import paper_1204_1586_amd as P
 
-HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "cpgrad.h")
+INCLUDE = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include")
 
 
 def _declared():
-    text = open(HEADER).read()
+    text = "".join(open(os.path.join(INCLUDE, h)).read() for h in sorted(os.listdir(INCLUDE)) if h.endswith(".h"))
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(\w+)\s*\(", text, flags=re.M)))
 
