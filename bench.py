@@ -37,6 +37,9 @@ def parse():
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain device copy of known size (for HBM counter calibration)")
+    ap.add_argument("--quick", action="store_true", help="only the main step timing (no comparisons)")
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_1204_1586_amd", "weights",
+                                                      "learned_step_cp4d_40x70.npz"))
     return ap.parse_args()
 
 
@@ -61,6 +64,65 @@ def cpu_baseline(pr, budget_s):
             break
     dt = (time.perf_counter() - t0) / reps
     return dt, reps, cores
+
+
+def als_to_fit(P, plan, Y, A0, tol=1e-6, max_sweeps=1000):
+    """Plain ALS from A0 until |fit_k - fit_{k-1}| < tol: sweeps and wall time."""
+    import torch
+    from paper_1204_1586_amd import learned
+    A = [a.clone() for a in A0]
+    r = learned.run_als(plan, Y, A, tol=tol, max_sweeps=max_sweeps)
+    return {"sweeps": r["sweeps"], "wall_s": round(r["wall_s"], 4), "fit": r["fit"], "converged": r["converged"]}
+
+
+def time_step(P, plan, Y, A0, steps, warmup):
+    """ms of one all-mode gradient and of one ALS sweep (HIP events on the plan's stream)."""
+    import torch
+    A = [a.clone() for a in A0]
+    G = [torch.empty_like(a) for a in A]
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        P.cpgrad_all_modes(plan, Y, A, G)
+        P.cpals_step(plan, Y, A, sync=False)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record(stream)
+    for _ in range(steps):
+        P.cpgrad_all_modes(plan, Y, A, G)
+    e[1].record(stream)
+    for _ in range(steps):
+        P.cpals_step(plan, Y, A, sync=False)
+    e[2].record(stream)
+    torch.cuda.synchronize()
+    return e[0].elapsed_time(e[1]) / steps, e[1].elapsed_time(e[2]) / steps
+
+
+def learned_comparison(P, weights, n_tensors=3, max_sweeps=3000):
+    """Plain FP32 ALS vs learned-step ALS to |delta fit| < 1e-6 on held-out
+    4-D 40x50x60x70 collinear tensors (same seeds and initial factors)."""
+    import numpy as np
+    import torch
+    import cpgen
+    from paper_1204_1586_amd import learned
+    d = np.load(weights)
+    net = learned.new_network(params=d["params"])
+    rows = []
+    for t in range(n_tensors):
+        pr = cpgen.make_problem("cp4d_40x70_learned", rep=10000 + t)
+        Y = torch.from_numpy(pr["y"]).cuda()
+        plan = P.cpgrad_plan(pr["dims"], pr["R"], "f32", "f32")
+        P.cpgrad_bind(plan, Y)
+        A0 = [torch.tensor(M, dtype=torch.float32).cuda() for M in pr["init"]]
+        r0 = learned.run_als(plan, Y, [a.clone() for a in A0], max_sweeps=max_sweeps)
+        r1 = learned.run_als(plan, Y, [a.clone() for a in A0], max_sweeps=max_sweeps, mlp=net)
+        rows.append({"rep": 10000 + t, "R": pr["R"], "plain_sweeps": r0["sweeps"], "plain_s": round(r0["wall_s"], 4),
+                     "plain_fit": r0["fit"], "learned_sweeps": r1["sweeps"], "learned_s": round(r1["wall_s"], 4),
+                     "learned_fit": r1["fit"], "fallback_rate": round(r1["fallback_rate"], 4)})
+    tot0 = sum(r["plain_sweeps"] for r in rows)
+    tot1 = sum(r["learned_sweeps"] for r in rows)
+    return {"tensors": rows, "trained_on_trajectories": int(d["trajectories"]),
+            "sweep_ratio": round(tot1 / tot0, 4),
+            "time_ratio": round(sum(r["learned_s"] for r in rows) / sum(r["plain_s"] for r in rows), 4)}
 
 
 def calib_copy():
@@ -173,6 +235,18 @@ def main():
                      "avg_launch_ms": round(k_ms, 6), "launches": fused_n,
                      "alg_bytes_per_launch": alg_bytes_launch},
     }
+    if not args.quick and pr["storage"] == "f32":
+        # the same tensor through the bf16 matrix cores with the same-pass refinement
+        planb = P.cpgrad_plan(dims, R, "f32", "f32", "bf16_refined")
+        P.cpgrad_bind(planb, Y)
+        gb_ms, ab_ms = time_step(P, planb, Y, A0, args.steps, args.warmup)
+        out["bf16_refined"] = {"all_mode_gradient_ms": round(gb_ms, 5),
+                               "value": round(info["alg_flops"] / (gb_ms * 1e-3) / 1e9, 3),
+                               "als_iters_per_s": round(1e3 / ab_ms, 2)}
+        # plain FP32 vs BF16-refined ALS to |delta fit| < 1e-6 from the same start
+        out["fit_1e-6"] = {"f32": als_to_fit(P, plan, Y, A0), "bf16_refined": als_to_fit(P, planb, Y, A0)}
+        if os.path.exists(args.weights):
+            out["learned_step"] = learned_comparison(P, args.weights)
     if not args.no_cpu_baseline:
         dt, reps, cores = cpu_baseline(pr, args.cpu_budget_s)
         out["cpu_baseline"] = {"value": round(info["alg_flops"] / dt / 1e9, 4), "unit": "GFLOP/s", "cores": cores,

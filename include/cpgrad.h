@@ -83,9 +83,11 @@ typedef enum {
                                   3.8); 0 restores the default                         */
     CPG_OPT_KERNEL = 2,        /* 0 = automatic, 1 = force the generic vector-ALU
                                   contraction, 2 = force the MFMA contraction           */
-    CPG_OPT_PROFILE = 3        /* 1: bracket every big-contraction launch with a pair of
+    CPG_OPT_PROFILE = 3,       /* 1: bracket every big-contraction launch with a pair of
                                   HIP events on the plan's stream (read them with
                                   cpgrad_profile_read); 0: off (default)               */
+    CPG_OPT_MFMA_COLS = 4      /* columns of Y per block of the matrix-core contractions
+                                  (a multiple of 32); 0 = automatic (default)           */
 } cpg_option;
 
 /* Create a plan for tensors of shape dims[0..N-1] (dims[0] = I_1 is the fastest
@@ -116,9 +118,10 @@ int cpgrad_set_option(cpgrad_plan_t p, int option, int64_t value);
 
 /* With CPG_OPT_PROFILE on: wait for the plan's stream and return the summed
  * duration (milliseconds, HIP events) and the number of big-contraction
- * launches recorded since the last read, restricted to `roles` (1 = right
- * pass, 2 = left pass, 3 = fused all-mode pass, 0 = all); then clear the
- * records.  Errors: CPG_ERR_INVALID, CPG_ERR_HIP. */
+ * launches recorded since the option was last set, restricted to `roles`
+ * (1 = right pass, 2 = left pass, 3 = fused all-mode pass, 0 = all).  Setting
+ * CPG_OPT_PROFILE (to 0 or 1) clears the records.  Errors: CPG_ERR_INVALID,
+ * CPG_ERR_HIP. */
 int cpgrad_profile_read(cpgrad_plan_t p, int roles, double* total_ms, int64_t* launches);
 
 /* Bind a tensor: computes ||Y||_F^2 in float64 (needed by the cost of eq.

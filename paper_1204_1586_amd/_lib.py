@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_PKG, "libcpgrad.so")
 
 CPG_F64, CPG_F32, CPG_BF16 = 0, 1, 2
 CPG_MODE_NATIVE, CPG_MODE_BF16, CPG_MODE_BF16_REFINED = 0, 1, 2
-CPG_OPT_FORCE_NSTAR, CPG_OPT_KERNEL, CPG_OPT_PROFILE = 1, 2, 3
+CPG_OPT_FORCE_NSTAR, CPG_OPT_KERNEL, CPG_OPT_PROFILE, CPG_OPT_MFMA_COLS = 1, 2, 3, 4
 MAX_MODES, MAX_RANK = 16, 64
 
 STATUS = {0: "CPG_OK", -1: "CPG_ERR_INVALID", -2: "CPG_ERR_NOMEM", -3: "CPG_ERR_HIP", -4: "CPG_ERR_NOT_SPD",

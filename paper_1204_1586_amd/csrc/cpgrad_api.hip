@@ -22,6 +22,7 @@ struct cpgrad_plan_s {
     hipStream_t stream = nullptr;
     int nstar_auto = 1, nstar = 1;
     int force_nstar = 0, kernel_opt = 0;
+    int64_t opt_cols = 0;                  // MFMA column chunk override (0 = automatic)
     int64_t Jn[CPG_MAX_MODES + 1] = {0};   // Jn[n] = I_1 ... I_n   (Jn[0] = 1)
     int64_t Kn[CPG_MAX_MODES + 1] = {0};   // Kn[n] = I_{n+1} ... I_N (Kn[N] = 1)
     int64_t J = 0, K = 0, numel = 0;
@@ -98,7 +99,7 @@ static Tiling tile_valu(int64_t J, int64_t K, int R, int fdt, int roles) {
 
 // Tiling of one pass for the MFMA kernel: 256-row blocks, column chunks of
 // whole 32-column steps, about two blocks per compute unit.
-static Tiling tile_mfma(int64_t J, int64_t K, int R, int roles, int kernel) {
+static Tiling tile_mfma(int64_t J, int64_t K, int R, int roles, int kernel, int64_t cols) {
     Tiling t{};
     t.kernel = kernel;
     t.rt = 16 * (int)cdiv(R, 16);
@@ -107,7 +108,7 @@ static Tiling tile_mfma(int64_t J, int64_t K, int R, int roles, int kernel) {
     const int64_t steps = cdiv(K, 32);
     const int64_t target = 512;
     (void)roles;
-    t.ktb = std::max<int64_t>(1, cdiv(steps * t.n_jr, target));
+    t.ktb = cols > 0 ? cdiv(cols, 32) : std::max<int64_t>(1, cdiv(steps * t.n_jr, target));
     t.n_kc = cdiv(steps, t.ktb);
     return t;
 }
@@ -122,7 +123,7 @@ static int mfma_kind(const cpgrad_plan_s* p) {
 
 static Tiling tile_pass(const cpgrad_plan_s* p, int roles) {
     const int kind = mfma_kind(p);
-    if (kind) return tile_mfma(p->J, p->K, p->R, roles, kind);
+    if (kind) return tile_mfma(p->J, p->K, p->R, roles, kind, p->opt_cols);
     return tile_valu(p->J, p->K, p->R, p->fdt, roles);
 }
 
@@ -715,7 +716,6 @@ int cpgrad_profile_read(cpgrad_plan_t p, int roles, double* total_ms, int64_t* l
         tot += ms;
         ++cnt;
     }
-    p->ev_used = 0;
     if (total_ms) *total_ms = tot;
     if (launches) *launches = cnt;
     return CPG_OK;
@@ -735,6 +735,9 @@ int cpgrad_set_option(cpgrad_plan_t p, int option, int64_t value) {
     } else if (option == CPG_OPT_KERNEL) {
         if (value < 0 || value > 2) return CPG_ERR_INVALID;
         p->kernel_opt = (int)value;
+    } else if (option == CPG_OPT_MFMA_COLS) {
+        if (value < 0 || value % 32 != 0 || value > (int64_t(1) << 30)) return CPG_ERR_INVALID;
+        p->opt_cols = value;
     } else {
         return CPG_ERR_INVALID;
     }
