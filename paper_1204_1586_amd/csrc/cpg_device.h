@@ -5,6 +5,14 @@
 
 namespace cpg {
 
+// Buffer resource over `bytes` bytes from `base` (raw addressing, stride 0).
+// Loads at offsets >= bytes return zero and stores there are dropped, so
+// ragged edges need no branches; kOOB is an offset that is always outside.
+constexpr uint32_t kOOB = 0x80000000u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
 // Khatri-Rao entry in float64: prod over modes m in [first, first+count) of
 // A^(m)(i_m, r), (i_first, ...) = unravel(idx) with the first mode fastest
 // (the row order of Notation 2.1's reverse-ordered products).

@@ -74,19 +74,26 @@ struct Tiling {
 hipError_t launch_contract_valu(int ydt, int fdt, const void* Y, int64_t J, int64_t K,
                                 const void* facset, int nstar, const Tiling& t, int roles, int ld,
                                 void* PRpart, void* PLpart, hipStream_t stream);
-// Outputs of the MFMA contraction: the split partials.
-struct MfmaOut {
+// Buffers of the MFMA contractions: the Khatri-Rao tables they read and the
+// split partials they write.
+struct MfmaBufs {
     float* PRpart;
     float* PLpart;
-    int ld;      // row stride (padded rank) of the partials
+    int ld;             // row stride (padded rank) of the partials and tables
+    const float* KRL;   // J x ld rows of the product over modes 1..n*
+    const float* KRR;   // K x ld rows of the product over modes n*+1..N
 };
-hipError_t launch_contract_mfma(int ydt, int mode, const void* Y, int64_t J, int64_t K,
-                                const FacSet<float>& fs, int nstar, const Tiling& t, int roles,
-                                const MfmaOut& out, hipStream_t stream);
+// Fill KRL / KRR (zero in columns R..ld-1) from the factor set.
+hipError_t launch_kr_tables(const FacSet<float>& fs, int nstar, int64_t J, int64_t K, int ld, float* KRL,
+                            float* KRR, hipStream_t stream);
+hipError_t launch_contract_mfma(int ydt, int mode, const void* Y, int64_t J, int64_t K, const Tiling& t,
+                                int roles, const MfmaBufs& bufs, hipStream_t stream);
 hipError_t launch_contract_bf16(int ydt, int mode, const void* Y, int64_t J, int64_t K,
                                 const FacSet<float>& fs, int nstar, const Tiling& t, int roles,
-                                const MfmaOut& out, hipStream_t stream);
+                                const MfmaBufs& bufs, hipStream_t stream);
 bool mfma_supported(int ydt, int fdt, int mode, int R);
+// widest column chunk (a multiple of 32) the float32 MFMA kernel holds in LDS
+int64_t mfma_f32_max_cols(int rt, int roles);
 
 // out[row][r] = sum_p parts[p][row][r] over rows x ld entries (float64, fixed order)
 hipError_t launch_reduce_parts(int fdt, const void* parts, int64_t nparts, int64_t rows, int ld,

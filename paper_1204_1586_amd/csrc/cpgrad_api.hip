@@ -36,6 +36,8 @@ struct cpgrad_plan_s {
     void* chain[4] = {nullptr, nullptr, nullptr, nullptr};
     void* PRpart = nullptr;
     void* PLpart = nullptr;
+    float* KRL = nullptr;     // Khatri-Rao tables of the MFMA contractions (J x ld, K x ld)
+    float* KRR = nullptr;
     void* Gtmp = nullptr;
     double* grams = nullptr;
     double* scal = nullptr;   // [0]=||Y||^2 [2]=cost [3]=fit [4]=inner [5]=||Yhat||^2 [6]=inner(cp_fit)
@@ -107,15 +109,19 @@ static Tiling tile_mfma(int64_t J, int64_t K, int R, int roles, int kernel, int6
     t.n_jr = cdiv(J, 256);
     const int64_t steps = cdiv(K, 32);
     const int64_t target = 512;
-    (void)roles;
     t.ktb = cols > 0 ? cdiv(cols, 32) : std::max<int64_t>(1, cdiv(steps * t.n_jr, target));
+    if (kernel == 2) {
+        // LDS holds the chunk's KR_R rows; a chunk of Y spans < 2^31 bytes (32-bit buffer offsets)
+        t.ktb = std::min<int64_t>(t.ktb, mfma_f32_max_cols(t.rt, roles) / 32);
+        t.ktb = std::max<int64_t>(1, std::min<int64_t>(t.ktb, ((int64_t(1) << 31) - 1) / (J * 4 * 32)));
+    }
     t.n_kc = cdiv(steps, t.ktb);
     return t;
 }
 
 // 0 = generic kernel, 2 = float32 MFMA, 3 = bf16 MFMA (reduced-precision modes)
 static int mfma_kind(const cpgrad_plan_s* p) {
-    if (p->kernel_opt == 1 || p->J >= (int64_t(1) << 31)) return 0;
+    if (p->kernel_opt == 1 || p->J * 4 * 32 >= (int64_t(1) << 31)) return 0;
     if (p->mode == CPG_MODE_NATIVE)
         return (p->ydt == CPG_F32 && p->fdt == CPG_F32 && (p->J % 4) == 0) ? 2 : 0;
     return (p->fdt == CPG_F32 && (p->ydt == CPG_F32 || p->ydt == CPG_BF16) && (p->J % 8) == 0) ? 3 : 0;
@@ -162,6 +168,9 @@ static int configure(cpgrad_plan_s* p) {
     const size_t oC3 = off;     off += al(chain_rows * R * a);
     const size_t oPRp = off;    off += al(nkc * p->J * R * a);
     const size_t oPLp = off;    off += al(njr * p->K * R * a);
+    const bool tables = p->t_fused.kernel == 2 || p->t_right.kernel == 2 || p->t_left.kernel == 2;
+    const size_t oKL = off;     off += tables ? al(p->J * R * 4) : 0;
+    const size_t oKR = off;     off += tables ? al(p->K * R * 4) : 0;
     const size_t oG = off;      off += al(maxI * R * a);
     const size_t oGr = off;     off += al((size_t)N * p->R * p->R * 8);
     const size_t oS = off;      off += al(16 * 8);
@@ -186,6 +195,8 @@ static int configure(cpgrad_plan_s* p) {
     p->chain[3] = b + oC3;
     p->PRpart = b + oPRp;
     p->PLpart = b + oPLp;
+    p->KRL = tables ? (float*)(b + oKL) : nullptr;
+    p->KRR = tables ? (float*)(b + oKR) : nullptr;
     p->Gtmp = b + oG;
     p->grams = (double*)(b + oGr);
     p->scal = (double*)(b + oS);
@@ -230,10 +241,12 @@ static hipError_t launch_contract(cpgrad_plan_s* p, const void* Y, const AnyFacS
                                   int roles) {
     if (t.n_kc > 65535) return hipErrorInvalidConfiguration;
     if (t.kernel == 2 || t.kernel == 3) {
-        MfmaOut o{(float*)p->PRpart, (float*)p->PLpart, p->ld};
+        MfmaBufs o{(float*)p->PRpart, (float*)p->PLpart, p->ld, p->KRL, p->KRR};
         if (t.kernel == 3)
             return launch_contract_bf16(p->ydt, p->mode, Y, p->J, p->K, fs.f, p->nstar, t, roles, o, p->stream);
-        return launch_contract_mfma(p->ydt, p->mode, Y, p->J, p->K, fs.f, p->nstar, t, roles, o, p->stream);
+        hipError_t e = launch_kr_tables(fs.f, p->nstar, p->J, p->K, p->ld, p->KRL, p->KRR, p->stream);
+        if (e != hipSuccess) return e;
+        return launch_contract_mfma(p->ydt, p->mode, Y, p->J, p->K, t, roles, o, p->stream);
     }
     return launch_contract_valu(p->ydt, p->fdt, Y, p->J, p->K, fs.ptr(p->fdt), p->nstar, t, roles, p->ld,
                                 p->PRpart, p->PLpart, p->stream);

@@ -267,7 +267,7 @@ __global__ __launch_bounds__(256) void k_contract_bf16(const void* __restrict__ 
 
 template <bool TYF, int NRT, bool REFINE>
 static hipError_t launch_b16_roles(const void* Y, int64_t J, int64_t K, const FacSet<float>& fs, int nstar,
-                                   const Tiling& t, int roles, const MfmaOut& o, hipStream_t s) {
+                                   const Tiling& t, int roles, const MfmaBufs& o, hipStream_t s) {
     dim3 grid((unsigned)t.n_jr, (unsigned)t.n_kc);
     const int64_t kcols = t.ktb * kB16Step;
     if (roles == 3)
@@ -286,7 +286,7 @@ static hipError_t launch_b16_roles(const void* Y, int64_t J, int64_t K, const Fa
 
 template <bool TYF, bool REFINE>
 static hipError_t launch_b16_nrt(const void* Y, int64_t J, int64_t K, const FacSet<float>& fs, int nstar,
-                                 const Tiling& t, int roles, const MfmaOut& o, hipStream_t s) {
+                                 const Tiling& t, int roles, const MfmaBufs& o, hipStream_t s) {
     switch (t.rt) {
         case 16: return launch_b16_roles<TYF, 1, REFINE>(Y, J, K, fs, nstar, t, roles, o, s);
         case 32: return launch_b16_roles<TYF, 2, REFINE>(Y, J, K, fs, nstar, t, roles, o, s);
@@ -297,7 +297,7 @@ static hipError_t launch_b16_nrt(const void* Y, int64_t J, int64_t K, const FacS
 }
 
 hipError_t launch_contract_bf16(int ydt, int mode, const void* Y, int64_t J, int64_t K, const FacSet<float>& fs,
-                                int nstar, const Tiling& t, int roles, const MfmaOut& o, hipStream_t stream) {
+                                int nstar, const Tiling& t, int roles, const MfmaBufs& o, hipStream_t stream) {
     if ((J % 8) != 0) return hipErrorInvalidValue;
     const bool refine = mode == CPG_MODE_BF16_REFINED;
     if (ydt == CPG_F32)

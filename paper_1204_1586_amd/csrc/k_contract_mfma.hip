@@ -12,12 +12,15 @@
 // reduces over rows, so each wave transposes its own 64 x 32 sub-tile
 // through a private LDS region and runs 16x16x4 MFMAs with the columns as
 // output rows; the four waves' partial sums meet in LDS and one partial row
-// block of P_L is written per step.  KR_R rows for the next step are built
-// cooperatively in LDS (double buffer, one block barrier per step); KR_L
-// rows of the block are built once into registers.  Partials go to
-// PRpart[block column][J][R] and PLpart[block row][K][R], reduced later in a
-// fixed order.
-#include "cpg_internal.h"
+// block of P_L is written per step.  The KR_R rows of the block's whole column
+// chunk are built once into LDS before the loop and KR_L rows of the block
+// once into registers, so the only global loads inside the loop are the Y
+// loads of the next step, which stay in flight across the step's MFMAs.
+// Partials go to PRpart[block column][J][R] and PLpart[block row][K][R],
+// reduced later in a fixed order.
+#include "cpg_device.h"
+
+#include <algorithm>
 
 namespace cpg {
 
@@ -26,6 +29,7 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 constexpr int kMfmaRows = 256;  // rows of Y per block (64 per wave)
 constexpr int kStep = 32;       // columns of Y per step
 constexpr int kTLd = 68;        // LDS leading dimension of the transposed sub-tile
+constexpr int kDepth = 2;       // steps of Y loads in flight ahead of the MFMAs
 
 __device__ __forceinline__ float kr_prod(const FacSet<float>& fs, int first, int count, int64_t idx, int r) {
     float v = 1.f;
@@ -44,13 +48,46 @@ __device__ __forceinline__ void lds_wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
+// Block barrier that orders LDS only: it does not wait for global loads in
+// flight (the next step's Y), unlike a full __syncthreads() fence.
+__device__ __forceinline__ void lds_block_sync() {
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// Khatri-Rao tables of the split (eq. 3.3, Notation 2.1): KRL (J x ld) holds
+// the rows of the product over modes 1..n*, KRR (K x ld) over modes n*+1..N,
+// zero in the padding columns R..ld-1.  One thread per entry.
+__global__ __launch_bounds__(256) void k_kr_tables(FacSet<float> fs, int nstar, int64_t J, int64_t K, int ld,
+                                                   float* __restrict__ KRL, float* __restrict__ KRR) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t nl = J * ld;
+    if (e >= nl + K * ld) return;
+    const bool left = e < nl;
+    const int64_t f = left ? e : e - nl;
+    const int64_t row = f / ld;
+    const int r = (int)(f - row * ld);
+    float v = 0.f;
+    if (r < fs.R) v = left ? kr_prod(fs, 0, nstar, row, r) : kr_prod(fs, nstar, fs.N - nstar, row, r);
+    (left ? KRL : KRR)[f] = v;
+}
+
+hipError_t launch_kr_tables(const FacSet<float>& fs, int nstar, int64_t J, int64_t K, int ld, float* KRL, float* KRR,
+                            hipStream_t stream) {
+    const int64_t total = (J + K) * ld;
+    const int64_t blocks = (total + 255) / 256;
+    if (blocks > INT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_kr_tables, dim3((unsigned)blocks), dim3(256), 0, stream, fs, nstar, J, K, ld, KRL, KRR);
+    return hipGetLastError();
+}
+
 template <int NRT, bool DO_R, bool DO_L>
 __global__ __launch_bounds__(256) void k_contract_mfma_f32(const float* __restrict__ Y, int64_t J, int64_t K,
-                                                            FacSet<float> fs, int nstar, int64_t kcols, int ld,
+                                                            int64_t kcols, int ld, const float* __restrict__ KRL,
+                                                            const float* __restrict__ KRR,
                                                             float* __restrict__ PRpart, float* __restrict__ PLpart) {
     constexpr int RT = NRT * 16;
     constexpr int KRLD = RT + 4;  // LDS row stride of the KR_R tile
-    __shared__ float sKRR[DO_R ? 2 : 1][DO_R ? kStep * KRLD : 1];
+    extern __shared__ float sKRR[];  // kcols x KRLD: KR_R rows of this block's column chunk
     __shared__ float sT[DO_L ? 4 : 1][DO_L ? kStep * kTLd : 1];
     __shared__ v4f sRed[DO_L ? 2 : 1][DO_L ? 4 * 2 * NRT * 64 : 1];
 
@@ -59,48 +96,71 @@ __global__ __launch_bounds__(256) void k_contract_mfma_f32(const float* __restri
     const int l = tid & 63;
     const int q = l >> 4;
     const int c16 = l & 15;
-    const int R = fs.R;
-    const int N = fs.N;
     const int64_t jb = (int64_t)blockIdx.x * kMfmaRows;
     const int64_t jw = jb + 64 * w;                 // first row of this wave
     const int64_t k_begin = (int64_t)blockIdx.y * kcols;
     const int64_t k_end = min(K, k_begin + kcols);
     const int64_t nsteps = (k_end - k_begin + kStep - 1) / kStep;
 
+    // Prologue.  Table loads go first and the first two steps of Y after them,
+    // so waiting for the tables leaves the Y loads in flight.  All loads are
+    // buffer loads without branches (rows or columns outside read as zero),
+    // which keeps the compiler's count of loads in flight exact.
+    //
     // KR_L operand of the left contraction: rows jw + 16q + s, columns rt*16 + c16
     float krl[DO_L ? NRT : 1][16];
     if (DO_L) {
+        const auto lrs_tab = buf_rsrc(KRL + jb * ld, (uint32_t)(min((int64_t)kMfmaRows, J - jb) * ld * 4));
 #pragma unroll
         for (int rt = 0; rt < NRT; ++rt) {
             const int r = rt * 16 + c16;
 #pragma unroll
             for (int s = 0; s < 16; ++s) {
-                const int64_t j = jw + 16 * q + s;
-                krl[rt][s] = (j < J && r < R) ? kr_prod(fs, 0, nstar, j, r) : 0.f;
+                const uint32_t off = r < ld ? (uint32_t)(((64 * w + 16 * q + s) * ld + r) * 4) : kOOB;
+                krl[rt][s] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(lrs_tab, (int)off, 0, 0));
             }
         }
     }
-
-    auto build_krr = [&](int buf, int64_t k0) {
-        for (int e = tid; e < kStep * RT; e += 256) {
-            const int kk = e / RT, r = e - (e / RT) * RT;
-            const int64_t k = k0 + kk;
-            sKRR[buf][kk * KRLD + r] = (k < k_end && r < R) ? kr_prod(fs, nstar, N - nstar, k, r) : 0.f;
+    // KR_R rows of the chunk, four ranks per float4 (ld is a multiple of 4)
+    constexpr int kKrBatch = 8;
+    const int n4 = (int)kcols * (RT / 4);
+    const auto rrs_tab = buf_rsrc(KRR + k_begin * ld, (uint32_t)((k_end - k_begin) * ld * 4));
+    auto load_krr = [&](v4f (&t)[kKrBatch], int base) {
+#pragma unroll
+        for (int u = 0; u < kKrBatch; ++u) {
+            const int e = base + u * 256 + tid;
+            const int kk = e / (RT / 4), r4 = (e - kk * (RT / 4)) * 4;
+            const uint32_t off = (e < n4 && r4 < ld) ? (uint32_t)((kk * ld + r4) * 4) : kOOB;
+            t[u] = __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(rrs_tab, (int)off, 0, 0));
         }
     };
+    auto store_krr = [&](const v4f (&t)[kKrBatch], int base) {
+#pragma unroll
+        for (int u = 0; u < kKrBatch; ++u) {
+            const int e = base + u * 256 + tid;
+            const int kk = e / (RT / 4), r4 = (e - kk * (RT / 4)) * 4;
+            if (e < n4) *(v4f*)(sKRR + kk * KRLD + r4) = t[u];
+        }
+    };
+    v4f krt[kKrBatch];
+    if (DO_R) load_krr(krt, 0);
 
-    // Y loads: lane (q, c16), slot c -> rows jw + 4*c16 .. +3 of column k0 + 4c + q
-    const bool row_ok = (jw + 4 * c16) < J;  // J % 4 == 0: a float4 is all in or all out
-    auto load_step = [&](v4f* dst, int64_t k0) {
+    // Y loads: lane (q, c16), slot c -> rows jw + 4*c16 .. +3 of column k0 + 4c + q,
+    // through a buffer resource over this block's column chunk: columns past
+    // the chunk and rows past J (lane offset kOOB) read as zero.
+    const auto yrs = buf_rsrc(Y + k_begin * J, (uint32_t)((k_end - k_begin) * J * 4));
+    const uint32_t lane_off = (jw + 4 * c16) < J ? (uint32_t)((jw + 4 * c16) * 4) : kOOB;
+    const uint32_t col_bytes = (uint32_t)(J * 4);
+    auto load_step = [&](v4f (&dst)[8], int64_t st) {
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
-            const int64_t k = k0 + 4 * c + q;
-            if (row_ok && k < k_end)
-                dst[c] = *(const v4f*)(Y + k * J + jw + 4 * c16);
-            else
-                dst[c] = v4f{0.f, 0.f, 0.f, 0.f};
+            const uint32_t off = lane_off + (uint32_t)(st * kStep + 4 * c + q) * col_bytes;
+            dst[c] = __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(yrs, (int)off, 0, 0));
         }
     };
+    // P_L partial stores of this block row, over the chunk's columns
+    const auto lrs = buf_rsrc(PLpart + ((int64_t)blockIdx.x * K + k_begin) * ld,
+                              (uint32_t)((k_end - k_begin) * ld * 4));
 
     v4f accR[DO_R ? 4 : 1][DO_R ? NRT : 1];
 #pragma unroll
@@ -108,23 +168,19 @@ __global__ __launch_bounds__(256) void k_contract_mfma_f32(const float* __restri
 #pragma unroll
         for (int rt = 0; rt < (DO_R ? NRT : 1); ++rt) accR[e][rt] = v4f{0.f, 0.f, 0.f, 0.f};
 
-    if (DO_R) build_krr(0, k_begin);
-    v4f cur[8], nxt[8];
-    load_step(cur, k_begin);
-    __syncthreads();
-
-    for (int64_t st = 0; st < nsteps; ++st) {
-        const int64_t k0 = k_begin + st * kStep;
+    // one step: MFMAs on `cur` (columns st*32 ..) while `nxt` receives step
+    // st + kDepth; steps st + 1 .. st + kDepth - 1 are already in flight
+    auto step = [&](v4f (&cur)[8], v4f (&nxt)[8], int64_t st) {
         const int buf = (int)(st & 1);
-        if (st + 1 < nsteps) load_step(nxt, k0 + kStep);
-
+        load_step(nxt, st + kDepth);
+        __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the step's MFMAs
         if (DO_R) {
             // P_R rows {4i + e} += Y(rows, k0 .. k0+31) KR_R(k0 .. k0+31, :)
 #pragma unroll
             for (int c = 0; c < 8; ++c) {
                 float b[NRT];
 #pragma unroll
-                for (int rt = 0; rt < NRT; ++rt) b[rt] = sKRR[buf][(4 * c + q) * KRLD + rt * 16 + c16];
+                for (int rt = 0; rt < NRT; ++rt) b[rt] = sKRR[(st * kStep + 4 * c + q) * KRLD + rt * 16 + c16];
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
 #pragma unroll
@@ -158,30 +214,51 @@ __global__ __launch_bounds__(256) void k_contract_mfma_f32(const float* __restri
             for (int kt = 0; kt < 2; ++kt)
 #pragma unroll
                 for (int rt = 0; rt < NRT; ++rt) sRed[buf][((w * 2 + kt) * NRT + rt) * 64 + l] = accL[kt][rt];
-        }
-        if (DO_R && st + 1 < nsteps) build_krr(buf ^ 1, k0 + kStep);
-        __syncthreads();
-        if (DO_L) {
-            // sum the four waves and write this block row's partial of P_L
-            for (int e = tid; e < 2 * NRT * 64; e += 256) {
-                const int lane = e & 63;
-                const int rt = (e >> 6) % NRT;
-                const int kt = (e >> 6) / NRT;
-                v4f s = sRed[buf][((0 * 2 + kt) * NRT + rt) * 64 + lane];
+            lds_block_sync();
+            // sum the four waves and write this block row's partial of P_L: every
+            // thread stores 2*NRT values (uniform count, so the wait for the next
+            // step's Y loads stays exact)
 #pragma unroll
-                for (int ww = 1; ww < 4; ++ww) s += sRed[buf][((ww * 2 + kt) * NRT + rt) * 64 + lane];
-                const int r = rt * 16 + (lane & 15);
-                if (r < ld) {
+            for (int j = 0; j < NRT; ++j) {
+                const int item = j * 128 + (tid >> 1);  // (kt, rt, lane) of the wave partials
+                const int lane = item & 63;
+                const int rt = (item >> 6) % NRT;
+                const int kt = (item >> 6) / NRT;
+                const int v0 = 2 * (tid & 1);
+                const float* src = (const float*)sRed[buf];
+                float s0 = 0.f, s1 = 0.f;
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int64_t k = k0 + kt * 16 + 4 * (lane >> 4) + v;
-                        if (k < k_end) PLpart[((int64_t)blockIdx.x * K + k) * ld + r] = s[v];
-                    }
+                for (int ww = 0; ww < 4; ++ww) {
+                    const float* e = src + (((ww * 2 + kt) * NRT + rt) * 64 + lane) * 4 + v0;
+                    s0 += e[0];
+                    s1 += e[1];
                 }
+                const int r = rt * 16 + (lane & 15);
+                const uint32_t off = r < ld
+                    ? (uint32_t)(((st * kStep + kt * 16 + 4 * (lane >> 4) + v0) * ld + r) * 4) : kOOB;
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(s0), lrs, (int)off, 0, 0);
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(s1), lrs, (int)(off + (uint32_t)(ld * 4)), 0, 0);
             }
         }
-#pragma unroll
-        for (int c = 0; c < 8; ++c) cur[c] = nxt[c];
+    };
+
+    // three register buffers rotate through the unrolled loop (no copies, so
+    // the loads of the two steps ahead stay in flight)
+    v4f b0[8], b1[8], b2[8];
+    load_step(b0, 0);
+    load_step(b1, 1);
+    if (DO_R) {
+        store_krr(krt, 0);
+        for (int base = kKrBatch * 256; base < n4; base += kKrBatch * 256) {  // wide chunks only
+            load_krr(krt, base);
+            store_krr(krt, base);
+        }
+    }
+    lds_block_sync();
+    for (int64_t st = 0; st < nsteps; st += 3) {
+        step(b0, b2, st);
+        if (st + 1 < nsteps) step(b1, b0, st + 1);
+        if (st + 2 < nsteps) step(b2, b1, st + 2);
     }
 
     if (DO_R) {
@@ -208,33 +285,59 @@ bool mfma_supported(int ydt, int fdt, int mode, int R) {
     return ydt == CPG_F32 && fdt == CPG_F32 && mode == CPG_MODE_NATIVE;
 }
 
-template <int NRT>
-static hipError_t launch_nrt(const float* Y, int64_t J, int64_t K, const FacSet<float>& fs, int nstar,
-                             const Tiling& t, int roles, const MfmaOut& o, hipStream_t s) {
-    dim3 grid((unsigned)t.n_jr, (unsigned)t.n_kc);
-    const int64_t kcols = t.ktb * kStep;
-    if (roles == 3)
-        hipLaunchKernelGGL((k_contract_mfma_f32<NRT, true, true>), grid, dim3(256), 0, s, Y, J, K, fs, nstar, kcols, o.ld,
-                           o.PRpart, o.PLpart);
-    else if (roles == 1)
-        hipLaunchKernelGGL((k_contract_mfma_f32<NRT, true, false>), grid, dim3(256), 0, s, Y, J, K, fs, nstar,
-                           kcols, o.ld, o.PRpart, o.PLpart);
-    else if (roles == 2)
-        hipLaunchKernelGGL((k_contract_mfma_f32<NRT, false, true>), grid, dim3(256), 0, s, Y, J, K, fs, nstar,
-                           kcols, o.ld, o.PRpart, o.PLpart);
-    else
-        return hipErrorInvalidValue;
+// LDS of one block: static transpose/reduction buffers plus the dynamic KR_R
+// chunk (kcols rows of RT + 4 floats).
+static constexpr int64_t static_lds(int nrt, bool do_l) {
+    return do_l ? (int64_t)4 * kStep * kTLd * 4 + (int64_t)2 * 4 * 2 * nrt * 64 * 16 : 0;
+}
+constexpr int64_t kLdsPerCu = 160 * 1024;
+
+int64_t mfma_f32_max_cols(int rt, int roles) {
+    const int nrt = rt / 16;
+    const int64_t row = (int64_t)(rt + 4) * 4;
+    const int64_t st = static_lds(nrt, (roles & 2) != 0);
+    // two blocks per CU while the rank tile allows it, else one
+    int64_t budget = kLdsPerCu / 2 - st;
+    if (budget < 4 * kStep * row) budget = kLdsPerCu - st;
+    return std::max<int64_t>(kStep, (budget / row) / kStep * kStep);
+}
+
+template <int NRT, bool DO_R, bool DO_L>
+static hipError_t launch_one(dim3 grid, const float* Y, int64_t J, int64_t K, int64_t kcols, const MfmaBufs& o,
+                             hipStream_t s) {
+    auto kern = k_contract_mfma_f32<NRT, DO_R, DO_L>;
+    const size_t dyn = DO_R ? (size_t)kcols * (NRT * 16 + 4) * sizeof(float) : 0;
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)(kLdsPerCu - static_lds(NRT, DO_L)));
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(kern, grid, dim3(256), dyn, s, Y, J, K, kcols, o.ld, o.KRL, o.KRR, o.PRpart, o.PLpart);
     return hipGetLastError();
 }
 
-hipError_t launch_contract_mfma(int ydt, int mode, const void* Y, int64_t J, int64_t K, const FacSet<float>& fs,
-                                int nstar, const Tiling& t, int roles, const MfmaOut& o, hipStream_t stream) {
+template <int NRT>
+static hipError_t launch_nrt(const float* Y, int64_t J, int64_t K, const Tiling& t, int roles, const MfmaBufs& o,
+                             hipStream_t s) {
+    dim3 grid((unsigned)t.n_jr, (unsigned)t.n_kc);
+    const int64_t kcols = t.ktb * kStep;
+    if (kcols > mfma_f32_max_cols(NRT * 16, roles)) return hipErrorInvalidValue;
+    if (roles == 3) return launch_one<NRT, true, true>(grid, Y, J, K, kcols, o, s);
+    if (roles == 1) return launch_one<NRT, true, false>(grid, Y, J, K, kcols, o, s);
+    if (roles == 2) return launch_one<NRT, false, true>(grid, Y, J, K, kcols, o, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_contract_mfma(int ydt, int mode, const void* Y, int64_t J, int64_t K, const Tiling& t, int roles,
+                                const MfmaBufs& o, hipStream_t stream) {
     if (ydt != CPG_F32 || mode != CPG_MODE_NATIVE || (J % 4) != 0) return hipErrorInvalidValue;
     switch (t.rt) {
-        case 16: return launch_nrt<1>((const float*)Y, J, K, fs, nstar, t, roles, o, stream);
-        case 32: return launch_nrt<2>((const float*)Y, J, K, fs, nstar, t, roles, o, stream);
-        case 48: return launch_nrt<3>((const float*)Y, J, K, fs, nstar, t, roles, o, stream);
-        case 64: return launch_nrt<4>((const float*)Y, J, K, fs, nstar, t, roles, o, stream);
+        case 16: return launch_nrt<1>((const float*)Y, J, K, t, roles, o, stream);
+        case 32: return launch_nrt<2>((const float*)Y, J, K, t, roles, o, stream);
+        case 48: return launch_nrt<3>((const float*)Y, J, K, t, roles, o, stream);
+        case 64: return launch_nrt<4>((const float*)Y, J, K, t, roles, o, stream);
         default: return hipErrorInvalidValue;
     }
 }
