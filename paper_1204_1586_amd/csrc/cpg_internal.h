@@ -39,7 +39,8 @@ struct EpiArgs {
     TC* Gout[CPG_MAX_MODES];       // gradients out (when !update), by 0-based mode
     int ld;                        // row stride of Z and the chain buffers
     int update;                    // apply eq. 2.14 after each gradient
-    int init;                      // first: all float64 Grams, clear flags
+    int init;                      // first: clear flags and (unless grams_ready) all float64 Grams
+    int grams_ready;               // the Grams were computed before this launch
     int cost;                      // last: cost of eq. 2.12 and fit from G^(N)
     double* grams;                 // [N][R][R] float64
     double* scal;                  // [0] = ||Y||^2 in; [2] cost, [3] fit, [4] <Y,Yhat>, [5] ||Yhat||^2 out
@@ -83,9 +84,13 @@ struct MfmaBufs {
     const float* KRL;   // J x ld rows of the product over modes 1..n*
     const float* KRR;   // K x ld rows of the product over modes n*+1..N
 };
-// Fill KRL / KRR (zero in columns R..ld-1) from the factor set.
+// Khatri-Rao tables (zero in columns R..ld-1) from the factor set: float32
+// KRL (J x ld, modes 1..n*) and KRR (K x ld, modes n*+1..N) for the MFMA
+// contractions, and float64 KRsR (J_{n*-1} x ld, modes 1..n*-1) and KRsL
+// (K_{n*+1} x ld, modes n*+2..N) for the first-mode gradients.  A null
+// table is skipped.
 hipError_t launch_kr_tables(const FacSet<float>& fs, int nstar, int64_t J, int64_t K, int ld, float* KRL,
-                            float* KRR, hipStream_t stream);
+                            float* KRR, double* KRsR, int64_t TsR, double* KRsL, int64_t TsL, hipStream_t stream);
 hipError_t launch_contract_mfma(int ydt, int mode, const void* Y, int64_t J, int64_t K, const Tiling& t,
                                 int roles, const MfmaBufs& bufs, hipStream_t stream);
 hipError_t launch_contract_bf16(int ydt, int mode, const void* Y, int64_t J, int64_t K,
@@ -94,6 +99,22 @@ hipError_t launch_contract_bf16(int ydt, int mode, const void* Y, int64_t J, int
 bool mfma_supported(int ydt, int fdt, int mode, int R);
 // widest column chunk (a multiple of 32) the float32 MFMA kernel holds in LDS
 int64_t mfma_f32_max_cols(int rt, int roles);
+
+// One side of the fused partial reduction + first-mode gradient (float32).
+struct ReduceFirst {
+    const float* parts;   // nparts x rows x ld split partials of the side's chain tensor
+    int64_t nparts;
+    int64_t rows;         // J (right) or K (left)
+    int ld;
+    int side;             // 0 = right: rows t + T*i;  1 = left: rows i + I*t
+    int64_t I;            // rows of the gradient (I_n of the side's first mode)
+    int64_t T;            // terms per gradient entry (J_{n-1} right, K_n left)
+    const double* KRs;    // T x ld float64 Khatri-Rao rows of the side's remaining modes
+    float* Z;             // rows x ld reduced chain tensor (out)
+    float* G;             // I x R gradient (out)
+};
+hipError_t launch_reduce_first(const ReduceFirst* sides, int nsides, const FacSet<float>& fs, double* grams,
+                               hipStream_t stream);
 
 // out[row][r] = sum_p parts[p][row][r] over rows x ld entries (float64, fixed order)
 hipError_t launch_reduce_parts(int fdt, const void* parts, int64_t nparts, int64_t rows, int ld,

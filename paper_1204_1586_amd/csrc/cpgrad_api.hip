@@ -38,6 +38,9 @@ struct cpgrad_plan_s {
     void* PLpart = nullptr;
     float* KRL = nullptr;     // Khatri-Rao tables of the MFMA contractions (J x ld, K x ld)
     float* KRR = nullptr;
+    double* KRsR = nullptr;   // float64 tables of the first gradients (J_{n*-1} x ld, K_{n*+1} x ld)
+    double* KRsL = nullptr;
+    bool fused_first = false; // partial reduction fused with each side's first gradient
     void* Gtmp = nullptr;
     double* grams = nullptr;
     double* scal = nullptr;   // [0]=||Y||^2 [2]=cost [3]=fit [4]=inner [5]=||Yhat||^2 [6]=inner(cp_fit)
@@ -141,6 +144,8 @@ static void release(cpgrad_plan_s* p) {
     p->ws_bytes = 0;
 }
 
+static bool fused_first_ok(const cpgrad_plan_s* p);
+
 // Choose n*, tile every pass and (re)allocate the workspace.
 static int configure(cpgrad_plan_s* p) {
     const int N = p->N;
@@ -171,6 +176,9 @@ static int configure(cpgrad_plan_s* p) {
     const bool tables = p->t_fused.kernel == 2 || p->t_right.kernel == 2 || p->t_left.kernel == 2;
     const size_t oKL = off;     off += tables ? al(p->J * R * 4) : 0;
     const size_t oKR = off;     off += tables ? al(p->K * R * 4) : 0;
+    p->fused_first = fused_first_ok(p);
+    const size_t oKsR = off;    off += p->fused_first ? al(p->Jn[p->nstar - 1] * R * 8) : 0;
+    const size_t oKsL = off;    off += p->fused_first ? al(p->Kn[p->nstar + 1] * R * 8) : 0;
     const size_t oG = off;      off += al(maxI * R * a);
     const size_t oGr = off;     off += al((size_t)N * p->R * p->R * 8);
     const size_t oS = off;      off += al(16 * 8);
@@ -197,6 +205,8 @@ static int configure(cpgrad_plan_s* p) {
     p->PLpart = b + oPLp;
     p->KRL = tables ? (float*)(b + oKL) : nullptr;
     p->KRR = tables ? (float*)(b + oKR) : nullptr;
+    p->KRsR = p->fused_first ? (double*)(b + oKsR) : nullptr;
+    p->KRsL = p->fused_first ? (double*)(b + oKsL) : nullptr;
     p->Gtmp = b + oG;
     p->grams = (double*)(b + oGr);
     p->scal = (double*)(b + oS);
@@ -242,10 +252,14 @@ static hipError_t launch_contract(cpgrad_plan_s* p, const void* Y, const AnyFacS
     if (t.n_kc > 65535) return hipErrorInvalidConfiguration;
     if (t.kernel == 2 || t.kernel == 3) {
         MfmaBufs o{(float*)p->PRpart, (float*)p->PLpart, p->ld, p->KRL, p->KRR};
+        const bool big = t.kernel == 2;
+        hipError_t e = launch_kr_tables(fs.f, p->nstar, p->J, p->K, p->ld, big && (roles & 2) ? p->KRL : nullptr,
+                                        big && (roles & 1) ? p->KRR : nullptr, (roles & 1) ? p->KRsR : nullptr,
+                                        p->Jn[p->nstar - 1], (roles & 2) ? p->KRsL : nullptr, p->Kn[p->nstar + 1],
+                                        p->stream);
+        if (e != hipSuccess) return e;
         if (t.kernel == 3)
             return launch_contract_bf16(p->ydt, p->mode, Y, p->J, p->K, fs.f, p->nstar, t, roles, o, p->stream);
-        hipError_t e = launch_kr_tables(fs.f, p->nstar, p->J, p->K, p->ld, p->KRL, p->KRR, p->stream);
-        if (e != hipSuccess) return e;
         return launch_contract_mfma(p->ydt, p->mode, Y, p->J, p->K, t, roles, o, p->stream);
     }
     return launch_contract_valu(p->ydt, p->fdt, Y, p->J, p->K, fs.ptr(p->fdt), p->nstar, t, roles, p->ld,
@@ -282,10 +296,28 @@ static hipError_t run_contract(cpgrad_plan_s* p, const void* Y, const AnyFacSet&
         if (_e != hipSuccess) return CPG_ERR_HIP;    \
     } while (0)
 
-// Reduce the partials of a pass into P_R and/or P_L.
-static int finish_partials(cpgrad_plan_s* p, const Tiling& t, int roles) {
-    if (roles & 1) CPG_TRY(launch_reduce_parts(p->fdt, p->PRpart, t.n_kc, p->J, p->ld, p->PR, p->stream));
-    if (roles & 2) CPG_TRY(launch_reduce_parts(p->fdt, p->PLpart, t.n_jr, p->K, p->ld, p->PL, p->stream));
+// Reduce the partials of a pass into P_R and/or P_L.  On the fused path a
+// side whose first gradient is wanted (Gr: G^(n*), Gl: G^(n*+1)) gets it from
+// the same kernel, which also computes every Gram when `grams` is set.
+// Returns CPG_OK; *fused tells whether the gradients were formed.
+static int finish_partials(cpgrad_plan_s* p, const FacSet<float>* fs, const Tiling& t, int roles, void* Gr = nullptr,
+                           void* Gl = nullptr, bool grams = false, bool* fused = nullptr) {
+    const bool fr = p->fused_first && fs && (roles & 1) && Gr;
+    const bool fl = p->fused_first && fs && (roles & 2) && Gl;
+    if (fused) *fused = fr || fl;
+    if (fr || fl) {
+        ReduceFirst sd[2];
+        int ns = 0;
+        if (fr)
+            sd[ns++] = ReduceFirst{(const float*)p->PRpart, t.n_kc, p->J, p->ld, 0, p->dims[p->nstar - 1],
+                                   p->Jn[p->nstar - 1], p->KRsR, (float*)p->PR, (float*)Gr};
+        if (fl)
+            sd[ns++] = ReduceFirst{(const float*)p->PLpart, t.n_jr, p->K, p->ld, 1, p->dims[p->nstar],
+                                   p->Kn[p->nstar + 1], p->KRsL, (float*)p->PL, (float*)Gl};
+        CPG_TRY(launch_reduce_first(sd, ns, *fs, grams ? p->grams : nullptr, p->stream));
+    }
+    if ((roles & 1) && !fr) CPG_TRY(launch_reduce_parts(p->fdt, p->PRpart, t.n_kc, p->J, p->ld, p->PR, p->stream));
+    if ((roles & 2) && !fl) CPG_TRY(launch_reduce_parts(p->fdt, p->PLpart, t.n_jr, p->K, p->ld, p->PL, p->stream));
     return CPG_OK;
 }
 
@@ -320,6 +352,14 @@ static bool epilogue_fits(const cpgrad_plan_s* p) {
     return true;
 }
 
+// The fused reduction + first gradients: float32 factors on an MFMA kind, and
+// both sides walked by the single-block epilogue.
+static bool fused_first_ok(const cpgrad_plan_s* p) {
+    const int kind = mfma_kind(p);
+    return (kind == 2 || kind == 3) && p->fdt == CPG_F32 && epilogue_fits(p) && side_first_small(p, 0, 4) &&
+           side_first_small(p, 1, 4);
+}
+
 template <typename TC>
 static EpiArgs<TC> epi_base(const cpgrad_plan_s* p, const FacSet<TC>& fs) {
     EpiArgs<TC> a{};
@@ -342,7 +382,7 @@ static EpiArgs<TC> epi_base(const cpgrad_plan_s* p, const FacSet<TC>& fs) {
 // the multi-block kernels, the rest in the epilogue.
 template <typename TC>
 static int run_side(cpgrad_plan_s* p, const FacSet<TC>& fs, int side, void* const* A, void* const* G, bool update,
-                    bool init, bool cost) {
+                    bool init, bool cost, const TC* Gpre0 = nullptr, bool grams_ready = false) {
     const int N = p->N, R = p->R;
     const int n_first = side == 0 ? p->nstar : p->nstar + 1;
     const int n_count = side == 0 ? p->nstar : N - p->nstar;
@@ -360,7 +400,9 @@ static int run_side(cpgrad_plan_s* p, const FacSet<TC>& fs, int side, void* cons
         a.buf[0] = (TC*)p->chain[0];
         a.buf[1] = (TC*)p->chain[1];
         a.init = init ? 1 : 0;
+        a.grams_ready = grams_ready ? 1 : 0;
         a.cost = cost ? 1 : 0;
+        a.Gpre = Gpre0;
         CPG_TRY(launch_epilogue(p->fdt, R, &a, 1, p->stream));
         return CPG_OK;
     }
@@ -400,7 +442,8 @@ static int run_side(cpgrad_plan_s* p, const FacSet<TC>& fs, int side, void* cons
 }
 
 template <typename TC>
-static int run_both_sides(cpgrad_plan_s* p, const FacSet<TC>& fs, void* const* A, void* const* G) {
+static int run_both_sides(cpgrad_plan_s* p, const FacSet<TC>& fs, void* const* A, void* const* G,
+                          bool pre = false) {
     if (side_first_small(p, 0, sizeof(TC)) && side_first_small(p, 1, sizeof(TC))) {
         // both chains are independent without updates: one launch, two blocks
         EpiArgs<TC> a[2] = {epi_base<TC>(p, fs), epi_base<TC>(p, fs)};
@@ -412,6 +455,7 @@ static int run_both_sides(cpgrad_plan_s* p, const FacSet<TC>& fs, void* const* A
             a[s].buf[0] = (TC*)p->chain[2 * s];
             a[s].buf[1] = (TC*)p->chain[2 * s + 1];
             for (int n = 0; n < p->N; ++n) a[s].Gout[n] = (TC*)G[n];
+            if (pre) a[s].Gpre = (const TC*)G[a[s].n_first - 1];   // formed by the fused reduction
         }
         CPG_TRY(launch_epilogue(p->fdt, p->R, a, 2, p->stream));
         return CPG_OK;
@@ -551,21 +595,25 @@ static int als_sweep_core(cpgrad_plan_s* p, const void* Y, void* const* A) {
     }
     // pass 1 over Y: P_R with the current A^(n*+1..N), then modes n*, ..., 1
     CPG_TRY(run_contract(p, Y, fs, p->t_right, 1));
-    int st = finish_partials(p, p->t_right, 1);
+    const FacSet<float>* fsf = p->fdt == CPG_F32 ? &fs.f : nullptr;
+    bool pre = false;
+    int st = finish_partials(p, fsf, p->t_right, 1, p->Gtmp, nullptr, true, &pre);
     if (st) return st;
     if (epi)
         st = p->fdt == CPG_F64 ? run_side<double>(p, fs.d, 0, A, nullptr, true, true, false)
-                               : run_side<float>(p, fs.f, 0, A, nullptr, true, true, false);
+                               : run_side<float>(p, fs.f, 0, A, nullptr, true, true, false,
+                                                 pre ? (const float*)p->Gtmp : nullptr, pre);
     else
         st = right_chain(p, fs, A, nullptr, true);
     if (st) return st;
     // pass 2 over Y: P_L with the updated A^(1..n*), then modes n*+1, ..., N and the cost
     CPG_TRY(run_contract(p, Y, fs, p->t_left, 2));
-    st = finish_partials(p, p->t_left, 2);
+    st = finish_partials(p, fsf, p->t_left, 2, nullptr, p->Gtmp, false, &pre);
     if (st) return st;
     if (epi) {
         st = p->fdt == CPG_F64 ? run_side<double>(p, fs.d, 1, A, nullptr, true, false, true)
-                               : run_side<float>(p, fs.f, 1, A, nullptr, true, false, true);
+                               : run_side<float>(p, fs.f, 1, A, nullptr, true, false, true,
+                                                 pre ? (const float*)p->Gtmp : nullptr);
         if (st) return st;
     } else {
         st = left_chain(p, fs, A, nullptr, true);
@@ -582,7 +630,7 @@ static int als_sweep_core(cpgrad_plan_s* p, const void* Y, void* const* A) {
 static int fit_core(cpgrad_plan_s* p, const void* Y, const AnyFacSet& fs, int slot) {
     CPG_TRY(launch_grams(p->fdt, fs.ptr(p->fdt), p->grams, p->stream));
     CPG_TRY(run_contract(p, Y, fs, p->t_right, 1));
-    int st = finish_partials(p, p->t_right, 1);
+    int st = finish_partials(p, nullptr, p->t_right, 1);
     if (st) return st;
     CPG_TRY(launch_inner_kr(p->fdt, p->PR, p->ld, p->J, fs.ptr(p->fdt), p->nstar, p->red, p->scal + 6,
                             p->stream));
@@ -776,11 +824,13 @@ int cpgrad_all_modes(cpgrad_plan_t p, const void* Y, const void* const* A, void*
         if (!A[n] || !G[n]) return CPG_ERR_INVALID;
     const AnyFacSet fs = facsets(p, A);
     CPG_TRY(run_contract(p, Y, fs, p->t_fused, 3));
-    int st = finish_partials(p, p->t_fused, 3);
+    bool pre = false;
+    int st = finish_partials(p, p->fdt == CPG_F32 ? &fs.f : nullptr, p->t_fused, 3, G[p->nstar - 1], G[p->nstar],
+                             false, &pre);
     if (st) return st;
     if (epilogue_fits(p)) {
         if (p->fdt == CPG_F64) return run_both_sides<double>(p, fs.d, (void* const*)A, G);
-        return run_both_sides<float>(p, fs.f, (void* const*)A, G);
+        return run_both_sides<float>(p, fs.f, (void* const*)A, G, pre);
     }
     st = right_chain(p, fs, (void* const*)A, G, false);
     if (st) return st;

@@ -9,6 +9,10 @@
 
 namespace cpg {
 
+struct d4s {
+    double x, y, z, w;
+};
+
 __device__ __forceinline__ double block_sum_256(double v, double* sbuf) {
     // sbuf: >= 256 doubles; returns the total in every thread
     const int tid = threadIdx.x;
@@ -54,6 +58,128 @@ hipError_t launch_reduce_parts(int fdt, const void* parts, int64_t nparts, int64
     else
         hipLaunchKernelGGL(k_reduce_parts<float>, dim3(nb), dim3(256), 0, s, (const float*)parts, nparts, n,
                            (float*)out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Partial reduction fused with the gradient of the side's first mode.  Block
+// i < I of a side reduces the chain-tensor rows of output row i over the
+// split partials (float64, fixed order p = 0, 1, ...), stores them rounded to
+// float32, and forms from the stored values
+//   right (eq. 3.12): G(i, r) = sum_t Z(t + T i, r) KRs(t, r),  T = J_{n-1}
+//   left  (eq. 3.16): G(i, r) = sum_t Z(i + I t, r) KRs(t, r),  T = K_n
+// with KRs the float64 Khatri-Rao rows of the side's remaining modes.  Extra
+// blocks (one per mode) compute the float64 Grams when `grams` is set.
+// ---------------------------------------------------------------------------
+constexpr int kRfBatch = 16;   // partial loads in flight per thread
+
+__device__ __forceinline__ void reduce_first_rows(const ReduceFirst& a, int64_t i, int R, d4s* spart) {
+    const int tid = threadIdx.x;
+    const int ld = a.ld;
+    const int nq = ld >> 2;                 // float4 columns of a row
+    int nqp = 1;
+    while (nqp < nq) nqp <<= 1;             // threads per term (a power of two <= 16)
+    const int q = tid & (nqp - 1);
+    const int tslot = tid / nqp;
+    const int tstep = 256 / nqp;
+    const int64_t rstride = a.side == 0 ? 1 : a.I;            // row of term t: rbase + t * rstride
+    const int64_t rbase = a.side == 0 ? a.T * i : i;
+    const int64_t pstride = a.rows * ld;                      // floats per partial
+    d4s g{0.0, 0.0, 0.0, 0.0};
+    if (q < nq) {
+        for (int64_t t = tslot; t < a.T; t += tstep) {
+            const int64_t row = rbase + t * rstride;
+            const float* src = a.parts + row * ld + 4 * q;
+            d4s acc{0.0, 0.0, 0.0, 0.0};
+            auto add = [&](const float4& v) {
+                acc.x += (double)v.x;
+                acc.y += (double)v.y;
+                acc.z += (double)v.z;
+                acc.w += (double)v.w;
+            };
+            // full batches without branches (so the loads stay in flight together), then the tail
+            int64_t p = 0;
+            for (; p + kRfBatch <= a.nparts; p += kRfBatch) {
+                float4 v[kRfBatch];
+#pragma unroll
+                for (int u = 0; u < kRfBatch; ++u) v[u] = *(const float4*)(src + (p + u) * pstride);
+#pragma unroll
+                for (int u = 0; u < kRfBatch; ++u) add(v[u]);
+            }
+            for (; p < a.nparts; ++p) add(*(const float4*)(src + p * pstride));
+            const float4 z{(float)acc.x, (float)acc.y, (float)acc.z, (float)acc.w};
+            *(float4*)(a.Z + row * ld + 4 * q) = z;
+            const double* w = a.KRs + t * ld + 4 * q;
+            g.x += (double)z.x * w[0];
+            g.y += (double)z.y * w[1];
+            g.z += (double)z.z * w[2];
+            g.w += (double)z.w * w[3];
+        }
+    }
+    spart[tid] = g;
+    __syncthreads();
+    for (int st = 128; st >= nqp; st >>= 1) {
+        if (tid < st) {
+            spart[tid].x += spart[tid + st].x;
+            spart[tid].y += spart[tid + st].y;
+            spart[tid].z += spart[tid + st].z;
+            spart[tid].w += spart[tid + st].w;
+        }
+        __syncthreads();
+    }
+    if (tid < nq) {
+        const d4s v = spart[tid];
+        const double vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (4 * tid + u < R) a.G[i * R + 4 * tid + u] = (float)vv[u];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_first(ReduceFirst s0, ReduceFirst s1, int64_t nb0, int64_t nb1,
+                                                      FacSet<float> fs, double* __restrict__ grams) {
+    __shared__ d4s spart[256];
+    const int64_t b = blockIdx.x;
+    if (b < nb0) {
+        reduce_first_rows(s0, b, fs.R, spart);
+    } else if (b < nb0 + nb1) {
+        reduce_first_rows(s1, b - nb0, fs.R, spart);
+    } else {
+        // float64 Gram of mode m, terms in index order
+        const int m = (int)(b - nb0 - nb1);
+        if (grams == nullptr || m >= fs.N) return;
+        const int R = fs.R;
+        const float* A = fs.A[m];
+        const int64_t I = fs.dims[m];
+        for (int e = threadIdx.x; e < R * R; e += 256) {
+            const int r = e / R, c = e - (e / R) * R;
+            double acc = 0.0;
+            int64_t i = 0;
+            for (; i + 8 <= I; i += 8) {   // terms in index order; loads of 8 rows at a time
+                float vr[8], vc[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    vr[u] = A[(i + u) * R + r];
+                    vc[u] = A[(i + u) * R + c];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) acc += (double)vr[u] * (double)vc[u];
+            }
+            for (; i < I; ++i) acc += (double)A[i * R + r] * (double)A[i * R + c];
+            grams[(int64_t)m * R * R + e] = acc;
+        }
+    }
+}
+
+hipError_t launch_reduce_first(const ReduceFirst* sides, int nsides, const FacSet<float>& fs, double* grams,
+                               hipStream_t s) {
+    if (nsides < 1 || nsides > 2) return hipErrorInvalidValue;
+    for (int k = 0; k < nsides; ++k)
+        if ((sides[k].ld & 3) != 0 || sides[k].ld > 64) return hipErrorInvalidValue;
+    const int64_t nb0 = sides[0].I, nb1 = nsides > 1 ? sides[1].I : 0;
+    const int64_t nb = nb0 + nb1 + (grams ? fs.N : 0);
+    hipLaunchKernelGGL(k_reduce_first, dim3((unsigned)nb), dim3(256), 0, s, sides[0], sides[nsides - 1], nb0, nb1,
+                       fs, grams);
     return hipGetLastError();
 }
 

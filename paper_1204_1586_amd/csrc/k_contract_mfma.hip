@@ -54,29 +54,59 @@ __device__ __forceinline__ void lds_block_sync() {
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
-// Khatri-Rao tables of the split (eq. 3.3, Notation 2.1): KRL (J x ld) holds
-// the rows of the product over modes 1..n*, KRR (K x ld) over modes n*+1..N,
-// zero in the padding columns R..ld-1.  One thread per entry.
+// Khatri-Rao tables (eq. 3.3, Notation 2.1), one thread per entry, zero in the
+// padding columns R..ld-1: float32 KRL (J x ld, product over modes 1..n*) and
+// KRR (K x ld, modes n*+1..N) read by the contractions; float64 KRsR
+// (J_{n*-1} x ld, modes 1..n*-1) and KRsL (K_{n*+1} x ld, modes n*+2..N)
+// weighting the first gradient of each side.  Entry ranges of the grid, in
+// order: KRL, KRR, KRsR, KRsL (a null table has no range).
 __global__ __launch_bounds__(256) void k_kr_tables(FacSet<float> fs, int nstar, int64_t J, int64_t K, int ld,
-                                                   float* __restrict__ KRL, float* __restrict__ KRR) {
-    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t nl = J * ld;
-    if (e >= nl + K * ld) return;
-    const bool left = e < nl;
-    const int64_t f = left ? e : e - nl;
-    const int64_t row = f / ld;
-    const int r = (int)(f - row * ld);
-    float v = 0.f;
-    if (r < fs.R) v = left ? kr_prod(fs, 0, nstar, row, r) : kr_prod(fs, nstar, fs.N - nstar, row, r);
-    (left ? KRL : KRR)[f] = v;
+                                                   float* __restrict__ KRL, float* __restrict__ KRR,
+                                                   double* __restrict__ KRsR, int64_t TsR,
+                                                   double* __restrict__ KRsL, int64_t TsL) {
+    int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int N = fs.N;
+    const int64_t nL = KRL ? J * ld : 0, nR = KRR ? K * ld : 0;
+    const int64_t nsR = KRsR ? TsR * ld : 0, nsL = KRsL ? TsL * ld : 0;
+    if (e < nL + nR) {
+        const bool left = e < nL;
+        const int64_t f = left ? e : e - nL;
+        const int64_t row = f / ld;
+        const int r = (int)(f - row * ld);
+        float v = 0.f;
+        if (r < fs.R) v = left ? kr_prod(fs, 0, nstar, row, r) : kr_prod(fs, nstar, N - nstar, row, r);
+        (left ? KRL : KRR)[f] = v;
+        return;
+    }
+    e -= nL + nR;
+    if (e >= nsR + nsL) return;
+    const bool right = e < nsR;
+    const int64_t f = right ? e : e - nsR;
+    int64_t idx = f / ld;
+    const int r = (int)(f - idx * ld);
+    const int first = right ? 0 : nstar + 1;
+    const int count = right ? nstar - 1 : N - nstar - 1;
+    double v = 0.0;
+    if (r < fs.R) {
+        v = 1.0;
+        for (int m = 0; m < count; ++m) {
+            const int64_t d = fs.dims[first + m];
+            const int64_t qd = idx / d;
+            v *= (double)fs.A[first + m][(idx - qd * d) * fs.R + r];
+            idx = qd;
+        }
+    }
+    (right ? KRsR : KRsL)[f] = v;
 }
 
 hipError_t launch_kr_tables(const FacSet<float>& fs, int nstar, int64_t J, int64_t K, int ld, float* KRL, float* KRR,
-                            hipStream_t stream) {
-    const int64_t total = (J + K) * ld;
+                            double* KRsR, int64_t TsR, double* KRsL, int64_t TsL, hipStream_t stream) {
+    const int64_t total = ((KRL ? J : 0) + (KRR ? K : 0) + (KRsR ? TsR : 0) + (KRsL ? TsL : 0)) * ld;
+    if (total == 0) return hipSuccess;
     const int64_t blocks = (total + 255) / 256;
     if (blocks > INT32_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_kr_tables, dim3((unsigned)blocks), dim3(256), 0, stream, fs, nstar, J, K, ld, KRL, KRR);
+    hipLaunchKernelGGL(k_kr_tables, dim3((unsigned)blocks), dim3(256), 0, stream, fs, nstar, J, K, ld, KRL, KRR, KRsR,
+                       TsR, KRsL, TsL);
     return hipGetLastError();
 }
 

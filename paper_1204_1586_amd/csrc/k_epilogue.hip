@@ -34,59 +34,133 @@ struct d4 {
 };
 __device__ __forceinline__ d4 operator+(d4 a, d4 b) { return d4{a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w}; }
 
-// four consecutive entries of a chain row (16-byte aligned: rows have stride ld = 4k)
-__device__ __forceinline__ d4 load4(const float* p) {
-    const float4 v = *(const float4*)p;
-    return d4{(double)v.x, (double)v.y, (double)v.z, (double)v.w};
-}
-__device__ __forceinline__ d4 load4(const double* p) {
-    const double2 a = *(const double2*)p, b = *(const double2*)(p + 2);
-    return d4{a.x, a.y, b.x, b.y};
-}
-__device__ __forceinline__ d4 mul4(d4 v, const double* w) { return d4{v.x * w[0], v.y * w[1], v.z * w[2], v.w * w[3]}; }
 
-// For O outputs (each four consecutive ranks) sum T weighted terms, term(o, t)
-// returning a d4; store(o, d4).  Few outputs: the terms of one output are split
-// over several threads and the parts summed in fixed order.
-template <typename Term, typename Store>
-__device__ __forceinline__ void block_sum_terms(int64_t O, int64_t T, Term term, Store store, d4* spart) {
-    const int tid = threadIdx.x;
-    if (O >= kEpiThreads) {
-        for (int64_t o = tid; o < O; o += kEpiThreads) {
-            d4 a0{0, 0, 0, 0}, a1{0, 0, 0, 0};
-            int64_t t = 0;
-            for (; t + 8 <= T; t += 8) {
-                const d4 v0 = term(o, t), v1 = term(o, t + 1), v2 = term(o, t + 2), v3 = term(o, t + 3);
-                const d4 v4 = term(o, t + 4), v5 = term(o, t + 5), v6 = term(o, t + 6), v7 = term(o, t + 7);
-                a0 = a0 + ((v0 + v1) + (v2 + v3));
-                a1 = a1 + ((v4 + v5) + (v6 + v7));
-            }
-            for (; t < T; ++t) a0 = a0 + term(o, t);
-            store(o, a0 + a1);
+// Four consecutive chain-tensor entries as loaded (16-byte aligned: rows
+// have stride ld = 4k), converted to float64 when weighted.
+template <typename TC>
+struct Raw4;
+template <>
+struct Raw4<float> {
+    float4 v;
+    __device__ __forceinline__ static Raw4 load(const float* p) { return Raw4{*(const float4*)p}; }
+    __device__ __forceinline__ d4 mul(const double* w) const {
+        return d4{(double)v.x * w[0], (double)v.y * w[1], (double)v.z * w[2], (double)v.w * w[3]};
+    }
+};
+template <>
+struct Raw4<double> {
+    double2 a, b;
+    __device__ __forceinline__ static Raw4 load(const double* p) {
+        return Raw4{*(const double2*)p, *(const double2*)(p + 2)};
+    }
+    __device__ __forceinline__ d4 mul(const double* w) const {
+        return d4{a.x * w[0], a.y * w[1], b.x * w[2], b.y * w[3]};
+    }
+};
+
+// LDS staging of n float64 entries, kStageBatch per thread in flight:
+// load(e) is called with a valid e (tails are clamped, so no load sits behind
+// a branch) and store(e, v) only for e < n.
+constexpr int kStageBatch = 4;
+template <typename Load, typename Store>
+__device__ __forceinline__ void stage_batched(int64_t n, Load load, Store store) {
+    for (int64_t e0 = threadIdx.x; e0 < n; e0 += kStageBatch * kEpiThreads) {
+        double v[kStageBatch];
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+            const int64_t e = e0 + u * kEpiThreads;
+            v[u] = load(e < n ? e : n - 1);
         }
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+            const int64_t e = e0 + u * kEpiThreads;
+            if (e < n) store(e, v[u]);
+        }
+    }
+}
+
+// Khatri-Rao rows t (Notation 2.1 order, modes first..first+count-1) into
+// sKR[t*ld + r], zero for r >= R; one mode at a time over a batch of entries,
+// so each mode costs one round of loads.
+template <typename TC>
+__device__ __forceinline__ void stage_kr(const FacSet<TC>& fs, int first, int count, int64_t T, int ld, double* sKR) {
+    const int R = fs.R;
+    const int64_t n = T * ld;
+    for (int64_t e0 = threadIdx.x; e0 < n; e0 += kStageBatch * kEpiThreads) {
+        double v[kStageBatch];
+        int64_t idx[kStageBatch];
+        int r[kStageBatch];
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+            const int64_t e = min(e0 + u * kEpiThreads, n - 1);
+            idx[u] = e / ld;
+            r[u] = (int)(e - idx[u] * ld);
+            v[u] = r[u] < R ? 1.0 : 0.0;
+            r[u] = r[u] < R ? r[u] : R - 1;
+        }
+        for (int m = 0; m < count; ++m) {
+            const int64_t d = fs.dims[first + m];
+            const TC* A = fs.A[first + m];
+            TC x[kStageBatch];
+#pragma unroll
+            for (int u = 0; u < kStageBatch; ++u) {
+                const int64_t q = idx[u] / d;
+                x[u] = A[(idx[u] - q * d) * R + r[u]];
+                idx[u] = q;
+            }
+#pragma unroll
+            for (int u = 0; u < kStageBatch; ++u) v[u] *= (double)x[u];
+        }
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+            const int64_t e = e0 + u * kEpiThreads;
+            if (e < n) sKR[e] = v[u];
+        }
+    }
+}
+
+constexpr int kEpiBatch = 16;   // chain-tensor loads in flight per thread
+
+// For O outputs (each four consecutive ranks) sum T weighted terms: term t of
+// output o is the four entries at addr(o, t) times the four float64 weights at
+// wt(o, t); store(o, d4) receives the sum.  Loads go out kEpiBatch at a time
+// before any is used (the chain tensors are streamed from memory by this one
+// block, so the loads in flight set its speed).  Few outputs: the terms of
+// one output are split over several threads and the parts summed in fixed
+// order.
+template <typename TC, typename Addr, typename Wt, typename Store>
+__device__ __forceinline__ void block_sum_terms(int64_t O, int64_t T, Addr addr, Wt wt, Store store, d4* spart) {
+    const int tid = threadIdx.x;
+    auto run = [&](int64_t o, int64_t t0, int64_t tstep) {
+        d4 a0{0, 0, 0, 0}, a1{0, 0, 0, 0};
+        int64_t t = t0;
+        // full batches without branches (so the loads stay in flight together), then the tail
+        for (; t + (kEpiBatch - 1) * tstep < T; t += kEpiBatch * tstep) {
+            Raw4<TC> v[kEpiBatch];
+#pragma unroll
+            for (int u = 0; u < kEpiBatch; ++u) v[u] = Raw4<TC>::load(addr(o, t + u * tstep));
+#pragma unroll
+            for (int u = 0; u < kEpiBatch; u += 2) {
+                a0 = a0 + v[u].mul(wt(o, t + u * tstep));
+                a1 = a1 + v[u + 1].mul(wt(o, t + (u + 1) * tstep));
+            }
+        }
+        for (; t < T; t += tstep) a0 = a0 + Raw4<TC>::load(addr(o, t)).mul(wt(o, t));
+        return a0 + a1;
+    };
+    if (O >= kEpiThreads) {
+        for (int64_t o = tid; o < O; o += kEpiThreads) store(o, run(o, 0, 1));
         __syncthreads();
     } else {
         const int g = kEpiThreads / (int)O;
-        d4 a0{0, 0, 0, 0}, a1{0, 0, 0, 0};
-        if (tid < g * O) {
-            const int64_t o = tid % O;
-            const int part = tid / (int)O;
-            int64_t t = part;
-            for (; t + 7 * g < T; t += 8 * g) {
-                const d4 v0 = term(o, t), v1 = term(o, t + g), v2 = term(o, t + 2 * g), v3 = term(o, t + 3 * g);
-                const d4 v4 = term(o, t + 4 * g), v5 = term(o, t + 5 * g), v6 = term(o, t + 6 * g),
-                         v7 = term(o, t + 7 * g);
-                a0 = a0 + ((v0 + v1) + (v2 + v3));
-                a1 = a1 + ((v4 + v5) + (v6 + v7));
-            }
-            for (; t < T; t += g) a0 = a0 + term(o, t);
-        }
-        spart[tid] = a0 + a1;
+        d4 acc{0, 0, 0, 0};
+        if (tid < g * O) acc = run(tid % O, tid / (int)O, g);
+        spart[tid] = acc;
         __syncthreads();
         if (tid < O) {
-            d4 acc{0, 0, 0, 0};
-            for (int p = 0; p < g; ++p) acc = acc + spart[p * O + tid];
-            store(tid, acc);
+            d4 tot{0, 0, 0, 0};
+            for (int p = 0; p < g; ++p) tot = tot + spart[p * O + tid];
+            store(tid, tot);
         }
         __syncthreads();
     }
@@ -102,18 +176,19 @@ __device__ __forceinline__ void block_grad(const TC* __restrict__ Z, int ld, con
     const int R = fs.R;
     const int nq = ld >> 2;
     {
-        for (int64_t e = threadIdx.x; e < T * ld; e += kEpiThreads) {
-            const int64_t t = e / ld;
-            const int r = (int)(e - t * ld);
-            sKR[e] = r < R ? kr_entry_d(fs, kr_first, kr_count, t, r) : 0.0;
-        }
+        stage_kr(fs, kr_first, kr_count, T, ld, sKR);
         __syncthreads();
-        block_sum_terms(
+        block_sum_terms<TC>(
             I * nq, T,
             [&](int64_t o, int64_t t) {
                 const int64_t i = o / nq;
                 const int q4 = 4 * (int)(o - i * nq);
-                return mul4(load4(Z + (i * si + t * st) * ld + q4), sKR + t * ld + q4);
+                return Z + (i * si + t * st) * ld + q4;
+            },
+            [&](int64_t o, int64_t t) {
+                const int64_t i = o / nq;
+                const int q4 = 4 * (int)(o - i * nq);
+                return (const double*)(sKR + t * ld + q4);
             },
             [&](int64_t o, d4 v) {
                 const int64_t i = o / nq;
@@ -134,19 +209,28 @@ __device__ __forceinline__ void block_ttv(const TC* __restrict__ in, TC* __restr
                                           int64_t lo_n, int64_t I, int64_t hi_n, int R, int ld, double* sA,
                                           d4* spart) {
     const int nq = ld >> 2;
-    for (int64_t e = threadIdx.x; e < I * ld; e += kEpiThreads) {
-        const int64_t i = e / ld;
-        const int r = (int)(e - i * ld);
-        sA[e] = r < R ? (double)a[i * R + r] : 0.0;
-    }
+    stage_batched(
+        I * ld,
+        [&](int64_t e) {
+            const int64_t i = e / ld;
+            const int r = (int)(e - i * ld);
+            const double x = (double)a[i * R + (r < R ? r : R - 1)];
+            return r < R ? x : 0.0;
+        },
+        [&](int64_t e, double v) { sA[e] = v; });
     __syncthreads();
-    block_sum_terms(
+    block_sum_terms<TC>(
         lo_n * hi_n * nq, I,
         [&](int64_t o, int64_t i) {
             const int64_t row = o / nq;
             const int q4 = 4 * (int)(o - row * nq);
             const int64_t hi = row / lo_n, lo = row - (row / lo_n) * lo_n;
-            return mul4(load4(in + (lo + lo_n * (i + I * hi)) * ld + q4), sA + i * ld + q4);
+            return in + (lo + lo_n * (i + I * hi)) * ld + q4;
+        },
+        [&](int64_t o, int64_t i) {
+            const int64_t row = o / nq;
+            const int q4 = 4 * (int)(o - row * nq);
+            return (const double*)(sA + i * ld + q4);
         },
         [&](int64_t o, d4 v) {
             const int64_t row = o / nq;
@@ -220,7 +304,8 @@ __device__ __forceinline__ void block_grams_all(const FacSet<TC>& fs, double* gr
         __syncthreads();
         for (int m = m0; m < m1; ++m) {
             const TC* A = fs.A[m];
-            for (int64_t e = threadIdx.x; e < I[m] * R; e += kEpiThreads) sA[off[m] + e] = (double)A[e];
+            stage_batched(
+                I[m] * R, [&](int64_t e) { return (double)A[e]; }, [&](int64_t e, double v) { sA[off[m] + e] = v; });
         }
         __syncthreads();
         block_gram_staged(sA, off, I, m0, m1, R, grams, spart);
@@ -228,13 +313,13 @@ __device__ __forceinline__ void block_grams_all(const FacSet<TC>& fs, double* gr
     }
 }
 
-// eq. 2.14 for mode n (0-based) with G^(n) in sG: A^(n) <- G Gamma^{-1} by a
+// eq. 2.14 for mode n (0-based) with G^(n) in sG, wide rank tiles: A^(n) <- G Gamma^{-1} by a
 // float64 Cholesky factorisation Gamma = L L^T (right-looking, one block
 // barrier per column; one retry with Gamma + 1e-12 tr(Gamma)/R I) and, for
 // every row g of G, the two triangular solves L z = g^T, L^T x = z.  Returns
 // false (leaving A^(n) and grams[n] untouched) if Gamma is not SPD.
 template <typename TC, int RT>
-__device__ __forceinline__ bool block_solve(const EpiArgs<TC>& a, int n, const double* sG, double* sGam, double* sL,
+__device__ __forceinline__ bool block_solve_lds(const EpiArgs<TC>& a, int n, const double* sG, double* sGam, double* sL,
                                             double* sA, double* spart, int* sOk) {
     constexpr int LD = RT + 1;
     const int tid = threadIdx.x;
@@ -333,6 +418,148 @@ __device__ __forceinline__ bool block_solve(const EpiArgs<TC>& a, int n, const d
     return true;
 }
 
+// 1/sqrt(d) in float64: hardware estimate refined by two Newton steps
+__device__ __forceinline__ double rsqrt_d(double d) {
+    double y = __builtin_amdgcn_rsq(d);
+    y = y * (1.5 - 0.5 * d * y * y);
+    y = y * (1.5 - 0.5 * d * y * y);
+    return y;
+}
+
+// Gamma (R x R, stride RT) = Hadamard product of the float64 Grams of every
+// mode but n (eq. 2.14).
+template <typename TC, int RT>
+__device__ __forceinline__ void block_gamma(const EpiArgs<TC>& a, int n, double* sGam) {
+    const int R = a.fs.R;
+    const int N = a.fs.N;
+    for (int e = threadIdx.x; e < R * R; e += kEpiThreads) {
+        double g[CPG_MAX_MODES];
+#pragma unroll
+        for (int k = 0; k < CPG_MAX_MODES; ++k) g[k] = (k < N && k != n) ? a.grams[(int64_t)k * R * R + e] : 1.0;
+        double v = 1.0;
+#pragma unroll
+        for (int k = 0; k < CPG_MAX_MODES; ++k) v *= g[k];
+        const int i = e / R;
+        sGam[i * RT + (e - i * R)] = v;
+    }
+}
+
+// One wave: W = L^{-1} for Gamma = L L^T (Gamma in sGam, stride RT), written
+// to sW (stride RT, zero above the diagonal).  Lane i keeps row i in
+// registers; entries of other rows arrive by lane broadcasts, so the whole
+// factorisation runs without block barriers.  Rows and columns R..RT-1 are
+// padded with the identity.  Cholesky in the row (dot-product) form
+//   L_jj = sqrt(Gamma_jj - sum_{k<j} L_jk^2),
+//   L_ij = (Gamma_ij - sum_{k<j} L_ik L_jk) / L_jj          (i > j),
+// then W row by row from W L = I, column j from RT-1 down to 0:
+//   W_ij = (delta_ij - sum_{k>j} W_ik L_kj) / L_jj,
+// overwriting L_ij once column j of L has been broadcast.  Returns false on a
+// pivot that is not positive and finite (uniform over the wave).
+template <int RT>
+__device__ __forceinline__ bool wave_chol_inverse(const double* sGam, int R, double jit, double* sW) {
+    const int l = threadIdx.x & 63;
+    double x[RT];
+#pragma unroll
+    for (int k = 0; k < RT; ++k)
+        x[k] = (l < R && k < R) ? sGam[l * RT + k] + (l == k ? jit : 0.0) : (l == k ? 1.0 : 0.0);
+    bool bad = false;
+    double dv = 1.0;   // lane j: 1 / L_jj
+#pragma unroll
+    for (int j = 0; j < RT; ++j) {
+        double v = readlane_d(x[j], j);
+        double t = x[j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) {
+            const double Ljk = readlane_d(x[k], j);
+            v -= Ljk * Ljk;
+            t -= x[k] * Ljk;
+        }
+        bad = bad || !(v > 0.0) || !isfinite(v);
+        const double y = rsqrt_d(v);
+        x[j] = l > j ? t * y : (l == j ? v * y : x[j]);
+        dv = l == j ? y : dv;
+        __builtin_amdgcn_sched_barrier(0);  // keep each step's broadcasts short-lived
+    }
+    if (bad) return false;
+#pragma unroll
+    for (int j = RT - 1; j >= 0; --j) {
+        const double dj = readlane_d(dv, j);
+        double t = l == j ? 1.0 : 0.0;
+#pragma unroll
+        for (int k = j + 1; k < RT; ++k) t -= x[k] * readlane_d(x[j], k);
+        x[j] = l >= j ? t * dj : 0.0;
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (l < RT) {
+#pragma unroll
+        for (int k = 0; k < RT; ++k) sW[l * RT + k] = x[k];
+    }
+    return true;
+}
+
+// eq. 2.14 for mode n (0-based) with G^(n) in sG: A^(n) <- G Gamma^{-1}.
+// Gamma by the block; W = L^{-1} by one wave (one jittered retry with
+// Gamma + 1e-12 tr(Gamma)/R I); Gamma^{-1} = W^T W and A^(n) = G Gamma^{-1}
+// by the block, then the Gram of the new factor: five block barriers per
+// mode.  Returns false (leaving A^(n) and grams[n] untouched) if Gamma is not
+// positive definite.
+template <typename TC, int RT>
+__device__ __forceinline__ bool block_solve(const EpiArgs<TC>& a, int n, const double* sG, double* sGam, double* sL,
+                                            double* sA, double* spart, int* sOk) {
+    if constexpr (RT > 16) {
+        return block_solve_lds<TC, RT>(a, n, sG, sGam, sL, sA, spart, sOk);
+    } else {
+        const int tid = threadIdx.x;
+        const int R = a.fs.R;
+        const int64_t I = a.fs.dims[n];
+        block_gamma<TC, RT>(a, n, sGam);
+        __syncthreads();
+        CPG_EPI_MARK(20);
+        if (tid < 64) {
+            double tr = 0.0;
+            for (int c = 0; c < R; ++c) tr += sGam[c * RT + c];
+            bool good = wave_chol_inverse<RT>(sGam, R, 0.0, sL);
+            if (!good) good = wave_chol_inverse<RT>(sGam, R, 1e-12 * tr / R, sL);
+            if (tid == 0) *sOk = good ? 1 : 0;
+        }
+        __syncthreads();
+        CPG_EPI_MARK(21);
+        if (!*sOk) return false;
+        // Gamma^{-1} = W^T W (W lower triangular), into sGam
+        for (int e = tid; e < R * R; e += kEpiThreads) {
+            const int r = e / R, c = e - (e / R) * R;
+            double acc = 0.0;
+            for (int i = (r > c ? r : c); i < R; ++i) acc += sL[i * RT + r] * sL[i * RT + c];
+            sGam[r * RT + c] = acc;
+        }
+        __syncthreads();
+        // A^(n) = G Gamma^{-1}
+        TC* A = (TC*)a.fs.A[n];
+        for (int64_t o = tid; o < I * R; o += kEpiThreads) {
+            const int64_t i = o / R;
+            const int c = (int)(o - i * R);
+            double a0 = 0.0, a1 = 0.0;
+            int s = 0;
+            for (; s + 2 <= R; s += 2) {
+                a0 += sG[i * RT + s] * sGam[s * RT + c];
+                a1 += sG[i * RT + s + 1] * sGam[(s + 1) * RT + c];
+            }
+            if (s < R) a0 += sG[i * RT + s] * sGam[s * RT + c];
+            const TC v = (TC)(a0 + a1);
+            A[o] = v;
+            sA[o] = (double)v;   // the stored (rounded) factor, for its Gram
+        }
+        __syncthreads();
+        CPG_EPI_MARK(22);
+        CPG_EPI_MARK(23);
+        int64_t In[CPG_MAX_MODES], offs[CPG_MAX_MODES];
+        In[n] = I;
+        offs[n] = 0;
+        block_gram_staged(sA, offs, In, n, n + 1, R, a.grams, spart);
+        return true;
+    }
+}
+
 template <typename TC, int RT>
 __device__ __forceinline__ void epilogue_body(const EpiArgs<TC>& a, double* sG, double* sGam, double* sW,
                                               double* spart, double* sKR, d4* spart4, int* sOkp) {
@@ -344,7 +571,7 @@ __device__ __forceinline__ void epilogue_body(const EpiArgs<TC>& a, double* sG, 
 
     if (a.init) {
         if (tid < 16) a.flags[tid] = 0;
-        block_grams_all(a.fs, a.grams, sKR, spart);
+        if (!a.grams_ready) block_grams_all(a.fs, a.grams, sKR, spart);
         CPG_EPI_MARK(1);
     }
 
@@ -384,7 +611,7 @@ __device__ __forceinline__ void epilogue_body(const EpiArgs<TC>& a, double* sG, 
             if (!block_solve<TC, RT>(a, n - 1, sG, sGam, sW, sKR, spart, &sOk)) {
                 if (tid == 0) atomicOr(a.flags, 1);
             }
-        } else {
+        } else if (!(step == 0 && a.Gpre == a.Gout[n - 1])) {
             TC* G = a.Gout[n - 1];
             for (int64_t o = tid; o < I * R; o += kEpiThreads) {
                 const int64_t i = o / R;
