@@ -466,14 +466,16 @@ __device__ __forceinline__ bool wave_chol_inverse(const double* sGam, int R, dou
     double dv = 1.0;   // lane j: 1 / L_jj
 #pragma unroll
     for (int j = 0; j < RT; ++j) {
-        double v = readlane_d(x[j], j);
-        double t = x[j];
+        // the dot products over k < j in four interleaved partial sums (short dependency chains)
+        double sv[4] = {0.0, 0.0, 0.0, 0.0}, st[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int k = 0; k < j; ++k) {
             const double Ljk = readlane_d(x[k], j);
-            v -= Ljk * Ljk;
-            t -= x[k] * Ljk;
+            sv[k & 3] += Ljk * Ljk;
+            st[k & 3] += x[k] * Ljk;
         }
+        const double v = readlane_d(x[j], j) - ((sv[0] + sv[1]) + (sv[2] + sv[3]));
+        const double t = x[j] - ((st[0] + st[1]) + (st[2] + st[3]));
         bad = bad || !(v > 0.0) || !isfinite(v);
         const double y = rsqrt_d(v);
         x[j] = l > j ? t * y : (l == j ? v * y : x[j]);
@@ -484,9 +486,10 @@ __device__ __forceinline__ bool wave_chol_inverse(const double* sGam, int R, dou
 #pragma unroll
     for (int j = RT - 1; j >= 0; --j) {
         const double dj = readlane_d(dv, j);
-        double t = l == j ? 1.0 : 0.0;
+        double st[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int k = j + 1; k < RT; ++k) t -= x[k] * readlane_d(x[j], k);
+        for (int k = j + 1; k < RT; ++k) st[k & 3] += x[k] * readlane_d(x[j], k);
+        const double t = (l == j ? 1.0 : 0.0) - ((st[0] + st[1]) + (st[2] + st[3]));
         x[j] = l >= j ? t * dj : 0.0;
         __builtin_amdgcn_sched_barrier(0);
     }
@@ -509,6 +512,7 @@ __device__ __forceinline__ bool block_solve(const EpiArgs<TC>& a, int n, const d
     if constexpr (RT > 16) {
         return block_solve_lds<TC, RT>(a, n, sG, sGam, sL, sA, spart, sOk);
     } else {
+        static_assert(2 * RT * RT <= kEpiThreads, "two threads per Gram entry");
         const int tid = threadIdx.x;
         const int R = a.fs.R;
         const int64_t I = a.fs.dims[n];
@@ -525,12 +529,14 @@ __device__ __forceinline__ bool block_solve(const EpiArgs<TC>& a, int n, const d
         __syncthreads();
         CPG_EPI_MARK(21);
         if (!*sOk) return false;
-        // Gamma^{-1} = W^T W (W lower triangular), into sGam
+        // Gamma^{-1} = W^T W into sGam (W: lower triangular, zero above the
+        // diagonal and in the padding, so the sums run over the whole tile)
         for (int e = tid; e < R * R; e += kEpiThreads) {
             const int r = e / R, c = e - (e / R) * R;
-            double acc = 0.0;
-            for (int i = (r > c ? r : c); i < R; ++i) acc += sL[i * RT + r] * sL[i * RT + c];
-            sGam[r * RT + c] = acc;
+            double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int i = 0; i < RT; ++i) acc[i & 3] += sL[i * RT + r] * sL[i * RT + c];
+            sGam[r * RT + c] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
         }
         __syncthreads();
         // A^(n) = G Gamma^{-1}
@@ -538,24 +544,36 @@ __device__ __forceinline__ bool block_solve(const EpiArgs<TC>& a, int n, const d
         for (int64_t o = tid; o < I * R; o += kEpiThreads) {
             const int64_t i = o / R;
             const int c = (int)(o - i * R);
-            double a0 = 0.0, a1 = 0.0;
-            int s = 0;
-            for (; s + 2 <= R; s += 2) {
-                a0 += sG[i * RT + s] * sGam[s * RT + c];
-                a1 += sG[i * RT + s + 1] * sGam[(s + 1) * RT + c];
-            }
-            if (s < R) a0 += sG[i * RT + s] * sGam[s * RT + c];
-            const TC v = (TC)(a0 + a1);
+            double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s = 0; s < RT; ++s)
+                if (s < R) acc[s & 3] += sG[i * RT + s] * sGam[s * RT + c];
+            const TC v = (TC)((acc[0] + acc[1]) + (acc[2] + acc[3]));
             A[o] = v;
             sA[o] = (double)v;   // the stored (rounded) factor, for its Gram
         }
         __syncthreads();
         CPG_EPI_MARK(22);
         CPG_EPI_MARK(23);
-        int64_t In[CPG_MAX_MODES], offs[CPG_MAX_MODES];
-        In[n] = I;
-        offs[n] = 0;
-        block_gram_staged(sA, offs, In, n, n + 1, R, a.grams, spart);
+        // Gram of the new factor: entry (r, c) over two threads, rows split by parity
+        {
+            const int E = R * R;
+            double acc[4] = {0.0, 0.0, 0.0, 0.0};
+            if (tid < 2 * E) {
+                const int e = tid % E, h = tid / E;
+                const int r = e / R, c = e - (e / R) * R;
+                int64_t i = h;
+                for (; i + 6 < I; i += 8) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) acc[u] += sA[(i + 2 * u) * R + r] * sA[(i + 2 * u) * R + c];
+                }
+                for (; i < I; i += 2) acc[0] += sA[i * R + r] * sA[i * R + c];
+            }
+            spart[tid] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+            __syncthreads();
+            if (tid < E) a.grams[(int64_t)n * E + tid] = spart[tid] + spart[tid + E];
+            __syncthreads();
+        }
         return true;
     }
 }
