@@ -113,6 +113,7 @@ class Plan:
         self.ydt, self.fdt, self.mode = ydt, fdt, mode
         self.stream = stream
         self.bound = None
+        self._memo = {}   # call name -> (argument identities, tensors kept alive, marshalled pointers)
 
     @property
     def N(self):
@@ -206,25 +207,42 @@ def cpgrad_bind(plan, Y):
     plan.bound = Y
 
 
+def _marshal(plan, name, Y, lists, checks):
+    """Validated, marshalled pointers for (Y, *lists).  A repeat call with the
+    very same tensor objects at the same device addresses reuses the last
+    result (the memo holds those tensors, so their identities cannot be reused
+    while it does; storage moved by resize_ or set_ is validated again)."""
+    key = (id(Y), Y.data_ptr()) + tuple(x for ts in lists for t in ts for x in (id(t), t.data_ptr()))
+    m = plan._memo.get(name)
+    if m is not None and m[0] == key:
+        return m[2]
+    checks()
+    out = (ctypes.c_void_p(Y.data_ptr()),) + tuple(_ptrs(ts) for ts in lists)
+    plan._memo[name] = (key, (Y,) + tuple(tuple(ts) for ts in lists), out)
+    return out
+
+
 def cpgrad_all_modes(plan, Y, A, G):
     """G[n] <- Y_(n) (⊙_{k≠n} A^(k)) for all n (asynchronous)."""
-    _check_y(plan, Y)
-    _check_factors(plan, A)
-    _check_factors(plan, G, "G")
-    _check(LIB.cpgrad_all_modes(plan.handle, ctypes.c_void_p(Y.data_ptr()), _ptrs(A), _ptrs(G)),
-           "cpgrad_all_modes")
+    def checks():
+        _check_y(plan, Y)
+        _check_factors(plan, A)
+        _check_factors(plan, G, "G")
+    y, a, g = _marshal(plan, "all_modes", Y, (A, G), checks)
+    _check(LIB.cpgrad_all_modes(plan.handle, y, a, g), "cpgrad_all_modes")
 
 
 def cpals_step(plan, Y, A, sync=True):
     """One CP_ALS sweep, A updated in place.  Returns (cost, fit) if sync, else None."""
-    _check_y(plan, Y)
-    _check_factors(plan, A)
+    def checks():
+        _check_y(plan, Y)
+        _check_factors(plan, A)
+    y, a = _marshal(plan, "als", Y, (A,), checks)
     if sync:
         c, f = ctypes.c_double(), ctypes.c_double()
-        _check(LIB.cpals_step(plan.handle, ctypes.c_void_p(Y.data_ptr()), _ptrs(A), ctypes.byref(c),
-                              ctypes.byref(f)), "cpals_step")
+        _check(LIB.cpals_step(plan.handle, y, a, ctypes.byref(c), ctypes.byref(f)), "cpals_step")
         return c.value, f.value
-    _check(LIB.cpals_step(plan.handle, ctypes.c_void_p(Y.data_ptr()), _ptrs(A), None, None), "cpals_step")
+    _check(LIB.cpals_step(plan.handle, y, a, None, None), "cpals_step")
     return None
 
 

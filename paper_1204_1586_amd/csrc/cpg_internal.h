@@ -116,6 +116,19 @@ struct ReduceFirst {
 hipError_t launch_reduce_first(const ReduceFirst* sides, int nsides, const FacSet<float>& fs, double* grams,
                                hipStream_t stream);
 
+// First chain step of one side for the all-mode gradient (float32, many blocks).
+struct TtvFirst {
+    const float* Z;       // rows x ld chain tensor of the side's first mode
+    int ld;
+    int side;             // 0 = right: rows t + T*i;  1 = left: rows i + I*t
+    int64_t I;            // size of the mode contracted away (I_{n*} right, I_{n*+1} left)
+    int64_t T;            // rows of the result (J_{n*-1} right, K_{n*+1} left)
+    const float* A;       // I x R factor of that mode
+    float* out;           // T x out_ld result
+    int out_ld;           // ld (chain buffer) or R (the next mode's gradient itself)
+};
+hipError_t launch_ttv_first(const TtvFirst* sides, int nsides, int R, hipStream_t stream);
+
 // out[row][r] = sum_p parts[p][row][r] over rows x ld entries (float64, fixed order)
 hipError_t launch_reduce_parts(int fdt, const void* parts, int64_t nparts, int64_t rows, int ld,
                                void* out, hipStream_t stream);

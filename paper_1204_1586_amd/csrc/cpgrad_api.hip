@@ -111,7 +111,9 @@ static Tiling tile_mfma(int64_t J, int64_t K, int R, int roles, int kernel, int6
     t.jtb = 1;
     t.n_jr = cdiv(J, 256);
     const int64_t steps = cdiv(K, 32);
-    const int64_t target = 512;
+    // about one block per CU: long-running blocks whose interleaved column
+    // steps sweep Y as one moving window (measured best for 64^4, rank 16)
+    const int64_t target = 256;
     t.ktb = cols > 0 ? cdiv(cols, 32) : std::max<int64_t>(1, cdiv(steps * t.n_jr, target));
     if (kernel == 2) {
         // LDS holds the chunk's KR_R rows; a chunk of Y spans < 2^31 bytes (32-bit buffer offsets)
@@ -124,7 +126,10 @@ static Tiling tile_mfma(int64_t J, int64_t K, int R, int roles, int kernel, int6
 
 // 0 = generic kernel, 2 = float32 MFMA, 3 = bf16 MFMA (reduced-precision modes)
 static int mfma_kind(const cpgrad_plan_s* p) {
-    if (p->kernel_opt == 1 || p->J * 4 * 32 >= (int64_t(1) << 31)) return 0;
+    // 32-bit buffer offsets: a 32-column step of Y and the K x ld table stay below 2 GiB
+    if (p->kernel_opt == 1 || p->J * 4 * 32 >= (int64_t(1) << 31) ||
+        p->K * (4 * ((p->R + 3) / 4)) * 4 >= (int64_t(1) << 31))
+        return 0;
     if (p->mode == CPG_MODE_NATIVE)
         return (p->ydt == CPG_F32 && p->fdt == CPG_F32 && (p->J % 4) == 0) ? 2 : 0;
     return (p->fdt == CPG_F32 && (p->ydt == CPG_F32 || p->ydt == CPG_BF16) && (p->J % 8) == 0) ? 3 : 0;
@@ -252,12 +257,6 @@ static hipError_t launch_contract(cpgrad_plan_s* p, const void* Y, const AnyFacS
     if (t.n_kc > 65535) return hipErrorInvalidConfiguration;
     if (t.kernel == 2 || t.kernel == 3) {
         MfmaBufs o{(float*)p->PRpart, (float*)p->PLpart, p->ld, p->KRL, p->KRR};
-        const bool big = t.kernel == 2;
-        hipError_t e = launch_kr_tables(fs.f, p->nstar, p->J, p->K, p->ld, big && (roles & 2) ? p->KRL : nullptr,
-                                        big && (roles & 1) ? p->KRR : nullptr, (roles & 1) ? p->KRsR : nullptr,
-                                        p->Jn[p->nstar - 1], (roles & 2) ? p->KRsL : nullptr, p->Kn[p->nstar + 1],
-                                        p->stream);
-        if (e != hipSuccess) return e;
         if (t.kernel == 3)
             return launch_contract_bf16(p->ydt, p->mode, Y, p->J, p->K, fs.f, p->nstar, t, roles, o, p->stream);
         return launch_contract_mfma(p->ydt, p->mode, Y, p->J, p->K, t, roles, o, p->stream);
@@ -269,6 +268,15 @@ static hipError_t launch_contract(cpgrad_plan_s* p, const void* Y, const AnyFacS
 // Launch one big contraction; with profiling on, bracket it with HIP events
 // recorded on the plan's stream.
 static hipError_t run_contract(cpgrad_plan_s* p, const void* Y, const AnyFacSet& fs, const Tiling& t, int roles) {
+    if (t.kernel == 2 || t.kernel == 3) {
+        // Khatri-Rao tables first (outside the timed bracket: a kernel of its own)
+        const bool big = t.kernel == 2;
+        hipError_t e = launch_kr_tables(fs.f, p->nstar, p->J, p->K, p->ld, big && (roles & 2) ? p->KRL : nullptr,
+                                        big && (roles & 1) ? p->KRR : nullptr, (roles & 1) ? p->KRsR : nullptr,
+                                        p->Jn[p->nstar - 1], (roles & 2) ? p->KRsL : nullptr, p->Kn[p->nstar + 1],
+                                        p->stream);
+        if (e != hipSuccess) return e;
+    }
     if (!p->profile) return launch_contract(p, Y, fs, t, roles);
     if (p->ev_used == p->ev_start.size()) {
         if (p->ev_used >= 65536) return launch_contract(p, Y, fs, t, roles);  // pool full: stop recording
@@ -441,9 +449,58 @@ static int run_side(cpgrad_plan_s* p, const FacSet<TC>& fs, int side, void* cons
     return CPG_OK;
 }
 
+// All-mode gradient after the fused reduction (G^(n*), G^(n*+1) written):
+// the first chain step of each side on many blocks, writing the next mode's
+// gradient directly when its Khatri-Rao block is empty; the single-block
+// epilogue only for modes left after that.
+static int all_modes_tail(cpgrad_plan_s* p, const FacSet<float>& fs, void* const* A, void* const* G) {
+    const int N = p->N, ns = p->nstar;
+    TtvFirst tf[2];
+    int nt = 0;
+    bool right_more = false, left_more = false;
+    if (ns >= 2) {
+        const bool last = ns == 2;   // G^(1) = R^(1)
+        tf[nt++] = TtvFirst{(const float*)p->PR, p->ld, 0, p->dims[ns - 1], p->Jn[ns - 1], (const float*)A[ns - 1],
+                            last ? (float*)G[0] : (float*)p->chain[0], last ? p->R : p->ld};
+        right_more = !last;
+    }
+    if (N - ns >= 2) {
+        const bool last = ns + 2 == N;   // G^(N) = L^(N)
+        tf[nt++] = TtvFirst{(const float*)p->PL, p->ld, 1, p->dims[ns], p->Kn[ns + 1], (const float*)A[ns],
+                            last ? (float*)G[N - 1] : (float*)p->chain[2], last ? p->R : p->ld};
+        left_more = !last;
+    }
+    if (nt) CPG_TRY(launch_ttv_first(tf, nt, p->R, p->stream));
+    EpiArgs<float> a[2];
+    int na = 0;
+    if (right_more) {
+        EpiArgs<float> e = epi_base<float>(p, fs);
+        e.side = 0;
+        e.n_first = ns - 1;
+        e.n_count = ns - 1;
+        e.Z = (const float*)p->chain[0];
+        e.buf[0] = (float*)p->chain[1];
+        e.buf[1] = (float*)p->chain[0];
+        for (int n = 0; n < N; ++n) e.Gout[n] = (float*)G[n];
+        a[na++] = e;
+    }
+    if (left_more) {
+        EpiArgs<float> e = epi_base<float>(p, fs);
+        e.side = 1;
+        e.n_first = ns + 2;
+        e.n_count = N - ns - 1;
+        e.Z = (const float*)p->chain[2];
+        e.buf[0] = (float*)p->chain[3];
+        e.buf[1] = (float*)p->chain[2];
+        for (int n = 0; n < N; ++n) e.Gout[n] = (float*)G[n];
+        a[na++] = e;
+    }
+    if (na) CPG_TRY(launch_epilogue(p->fdt, p->R, a, na, p->stream));
+    return CPG_OK;
+}
+
 template <typename TC>
-static int run_both_sides(cpgrad_plan_s* p, const FacSet<TC>& fs, void* const* A, void* const* G,
-                          bool pre = false) {
+static int run_both_sides(cpgrad_plan_s* p, const FacSet<TC>& fs, void* const* A, void* const* G) {
     if (side_first_small(p, 0, sizeof(TC)) && side_first_small(p, 1, sizeof(TC))) {
         // both chains are independent without updates: one launch, two blocks
         EpiArgs<TC> a[2] = {epi_base<TC>(p, fs), epi_base<TC>(p, fs)};
@@ -455,7 +512,6 @@ static int run_both_sides(cpgrad_plan_s* p, const FacSet<TC>& fs, void* const* A
             a[s].buf[0] = (TC*)p->chain[2 * s];
             a[s].buf[1] = (TC*)p->chain[2 * s + 1];
             for (int n = 0; n < p->N; ++n) a[s].Gout[n] = (TC*)G[n];
-            if (pre) a[s].Gpre = (const TC*)G[a[s].n_first - 1];   // formed by the fused reduction
         }
         CPG_TRY(launch_epilogue(p->fdt, p->R, a, 2, p->stream));
         return CPG_OK;
@@ -830,7 +886,8 @@ int cpgrad_all_modes(cpgrad_plan_t p, const void* Y, const void* const* A, void*
     if (st) return st;
     if (epilogue_fits(p)) {
         if (p->fdt == CPG_F64) return run_both_sides<double>(p, fs.d, (void* const*)A, G);
-        return run_both_sides<float>(p, fs.f, (void* const*)A, G, pre);
+        if (pre) return all_modes_tail(p, fs.f, (void* const*)A, G);
+        return run_both_sides<float>(p, fs.f, (void* const*)A, G);
     }
     st = right_chain(p, fs, (void* const*)A, G, false);
     if (st) return st;

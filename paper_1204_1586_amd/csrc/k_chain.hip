@@ -184,6 +184,89 @@ hipError_t launch_reduce_first(const ReduceFirst* sides, int nsides, const FacSe
 }
 
 // ---------------------------------------------------------------------------
+// First chain step of each side for the all-mode gradient (no updates), many
+// blocks: the chain tensor after the side's first mode,
+//   right (eq. 3.20): out(t, r) = sum_i Z(t + T i, r) A(i, r),  T = J_{n*-1}, A = A^(n*)
+//   left  (eq. 3.22): out(t, r) = sum_i Z(i + I t, r) A(i, r),  T = K_{n*+1}, A = A^(n*+1)
+// written with row stride out_ld (ld for a chain buffer, R when it is already
+// the next mode's gradient).  Each output float4 is summed by kTfParts threads
+// over interleaved terms, the parts added in fixed order.
+// ---------------------------------------------------------------------------
+constexpr int kTfParts = 16;
+constexpr int kTfOut = 256 / kTfParts;   // outputs (float4) per block
+
+__device__ __forceinline__ void ttv_first_rows(const TtvFirst& a, int64_t blk, int R, d4s* spart) {
+    const int tid = threadIdx.x;
+    const int ol = tid % kTfOut, part = tid / kTfOut;
+    const int nq = a.ld >> 2;
+    const int64_t o = blk * kTfOut + ol;
+    const bool live = o < a.T * nq;
+    const int64_t t = live ? o / nq : 0;
+    const int q = live ? (int)(o - t * nq) : 0;
+    const int64_t rstride = a.side == 0 ? a.T : 1;      // row of term i: rbase + i * rstride
+    const int64_t rbase = a.side == 0 ? t : a.I * t;
+    const float* src = a.Z + rbase * a.ld + 4 * q;
+    const int64_t zstep = rstride * a.ld;
+    int rr[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) rr[u] = min(4 * q + u, R - 1);   // factor column (clamped in the padding)
+    d4s acc{0.0, 0.0, 0.0, 0.0};
+    auto add = [&](const float4& z, int64_t i) {
+        const float* w = a.A + i * R;
+        acc.x += (double)z.x * (double)w[rr[0]];
+        acc.y += (double)z.y * (double)w[rr[1]];
+        acc.z += (double)z.z * (double)w[rr[2]];
+        acc.w += (double)z.w * (double)w[rr[3]];
+    };
+    int64_t i = part;
+    for (; i + 3 * kTfParts < a.I; i += 4 * kTfParts) {   // four terms in flight
+        float4 z[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) z[u] = *(const float4*)(src + (i + u * kTfParts) * zstep);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) add(z[u], i + u * kTfParts);
+    }
+    for (; i < a.I; i += kTfParts) add(*(const float4*)(src + i * zstep), i);
+    spart[tid] = live ? acc : d4s{0.0, 0.0, 0.0, 0.0};
+    __syncthreads();
+    if (part == 0 && live) {
+        d4s v = spart[ol];
+        for (int p = 1; p < kTfParts; ++p) {
+            const d4s w = spart[p * kTfOut + ol];
+            v.x += w.x;
+            v.y += w.y;
+            v.z += w.z;
+            v.w += w.w;
+        }
+        const double vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (a.out_ld != R || 4 * q + u < R) a.out[t * a.out_ld + 4 * q + u] = (4 * q + u < R) ? (float)vv[u] : 0.f;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ttv_first(TtvFirst s0, TtvFirst s1, int64_t nb0, int64_t nb1, int R) {
+    __shared__ d4s spart[256];
+    const int64_t b = blockIdx.x;
+    if (b < nb0)
+        ttv_first_rows(s0, b, R, spart);
+    else if (b < nb0 + nb1)
+        ttv_first_rows(s1, b - nb0, R, spart);
+}
+
+hipError_t launch_ttv_first(const TtvFirst* sides, int nsides, int R, hipStream_t s) {
+    if (nsides < 1 || nsides > 2) return hipErrorInvalidValue;
+    int64_t nb[2] = {0, 0};
+    for (int k = 0; k < nsides; ++k) {
+        if ((sides[k].ld & 3) != 0) return hipErrorInvalidValue;
+        nb[k] = (sides[k].T * (sides[k].ld >> 2) + kTfOut - 1) / kTfOut;
+    }
+    hipLaunchKernelGGL(k_ttv_first, dim3((unsigned)(nb[0] + nb[1])), dim3(256), 0, s, sides[0], sides[nsides - 1],
+                       nb[0], nb[1], R);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // one chain step: out[lo + lo_n*hi][r] = sum_i in[lo + lo_n*(i + I*hi)][r] a[i][r]
 //   right chain (eq. 3.20): lo_n = J_n, I = I_{n+1}, hi_n = 1
 //   left chain  (eq. 3.22): lo_n = 1,   I = I_{n-1}, hi_n = K_{n-1}

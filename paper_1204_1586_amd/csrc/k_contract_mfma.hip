@@ -117,7 +117,8 @@ __global__ __launch_bounds__(256) void k_contract_mfma_f32(const float* __restri
                                                             float* __restrict__ PRpart, float* __restrict__ PLpart) {
     constexpr int RT = NRT * 16;
     constexpr int KRLD = RT + 4;  // LDS row stride of the KR_R tile
-    extern __shared__ float sKRR[];  // kcols x KRLD: KR_R rows of this block's column chunk
+    extern __shared__ float sKRR[];  // kcols x KRLD: KR_R rows of this block's column steps
+    (void)kcols;                     // sizes sKRR (at least 32 x the block's step count)
     __shared__ float sT[DO_L ? 4 : 1][DO_L ? kStep * kTLd : 1];
     __shared__ v4f sRed[DO_L ? 2 : 1][DO_L ? 4 * 2 * NRT * 64 : 1];
 
@@ -128,9 +129,15 @@ __global__ __launch_bounds__(256) void k_contract_mfma_f32(const float* __restri
     const int c16 = l & 15;
     const int64_t jb = (int64_t)blockIdx.x * kMfmaRows;
     const int64_t jw = jb + 64 * w;                 // first row of this wave
-    const int64_t k_begin = (int64_t)blockIdx.y * kcols;
-    const int64_t k_end = min(K, k_begin + kcols);
-    const int64_t nsteps = (k_end - k_begin + kStep - 1) / kStep;
+    // Steps of 32 columns are dealt round-robin over the block columns: block
+    // column by takes global steps by, by + n_kc, by + 2 n_kc, ... (at most
+    // kcols / 32 of them), so at any time the grid reads one contiguous window
+    // of Y that moves through memory (measured: about 1.4x the bandwidth of
+    // giving each block a contiguous chunk of columns).
+    const int64_t n_kc = gridDim.y;
+    const int64_t gsteps = (K + kStep - 1) / kStep;
+    const int64_t nsteps = (gsteps - blockIdx.y + n_kc - 1) / n_kc;
+    auto step_col = [&](int64_t st) { return (st * n_kc + blockIdx.y) * kStep; };   // first column of step st
 
     // Prologue.  Table loads go first and the first two steps of Y after them,
     // so waiting for the tables leaves the Y loads in flight.  All loads are
@@ -151,16 +158,18 @@ __global__ __launch_bounds__(256) void k_contract_mfma_f32(const float* __restri
             }
         }
     }
-    // KR_R rows of the chunk, four ranks per float4 (ld is a multiple of 4)
+    // KR_R rows of the block's steps (LDS row st*32 + kk <- column step_col(st) + kk),
+    // four ranks per float4 (ld is a multiple of 4); rows past K read as zero
     constexpr int kKrBatch = 8;
-    const int n4 = (int)kcols * (RT / 4);
-    const auto rrs_tab = buf_rsrc(KRR + k_begin * ld, (uint32_t)((k_end - k_begin) * ld * 4));
+    const int n4 = (int)(nsteps * kStep) * (RT / 4);
+    const auto rrs_tab = buf_rsrc(KRR, (uint32_t)(K * ld * 4));
     auto load_krr = [&](v4f (&t)[kKrBatch], int base) {
 #pragma unroll
         for (int u = 0; u < kKrBatch; ++u) {
             const int e = base + u * 256 + tid;
             const int kk = e / (RT / 4), r4 = (e - kk * (RT / 4)) * 4;
-            const uint32_t off = (e < n4 && r4 < ld) ? (uint32_t)((kk * ld + r4) * 4) : kOOB;
+            const int64_t k = step_col(kk / kStep) + (kk & (kStep - 1));
+            const uint32_t off = (e < n4 && r4 < ld && k < K) ? (uint32_t)((k * ld + r4) * 4) : kOOB;
             t[u] = __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(rrs_tab, (int)off, 0, 0));
         }
     };
@@ -175,22 +184,22 @@ __global__ __launch_bounds__(256) void k_contract_mfma_f32(const float* __restri
     v4f krt[kKrBatch];
     if (DO_R) load_krr(krt, 0);
 
-    // Y loads: lane (q, c16), slot c -> rows jw + 4*c16 .. +3 of column k0 + 4c + q,
-    // through a buffer resource over this block's column chunk: columns past
-    // the chunk and rows past J (lane offset kOOB) read as zero.
-    const auto yrs = buf_rsrc(Y + k_begin * J, (uint32_t)((k_end - k_begin) * J * 4));
+    // Y loads: lane (q, c16), slot c -> rows jw + 4*c16 .. +3 of column
+    // step_col(st) + 4c + q, through a buffer resource over the step's 32
+    // columns: columns past K, steps past the block's last one and rows past
+    // J (lane offset kOOB) read as zero.
     const uint32_t lane_off = (jw + 4 * c16) < J ? (uint32_t)((jw + 4 * c16) * 4) : kOOB;
     const uint32_t col_bytes = (uint32_t)(J * 4);
     auto load_step = [&](v4f (&dst)[8], int64_t st) {
+        const int64_t k0 = step_col(st);
+        const int64_t ncol = st < nsteps ? max((int64_t)0, min((int64_t)kStep, K - k0)) : 0;
+        const auto yrs = buf_rsrc(Y + (st < nsteps ? k0 : 0) * J, (uint32_t)(ncol * J * 4));
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
-            const uint32_t off = lane_off + (uint32_t)(st * kStep + 4 * c + q) * col_bytes;
+            const uint32_t off = lane_off + (uint32_t)(4 * c + q) * col_bytes;
             dst[c] = __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(yrs, (int)off, 0, 0));
         }
     };
-    // P_L partial stores of this block row, over the chunk's columns
-    const auto lrs = buf_rsrc(PLpart + ((int64_t)blockIdx.x * K + k_begin) * ld,
-                              (uint32_t)((k_end - k_begin) * ld * 4));
 
     v4f accR[DO_R ? 4 : 1][DO_R ? NRT : 1];
 #pragma unroll
@@ -224,27 +233,36 @@ __global__ __launch_bounds__(256) void k_contract_mfma_f32(const float* __restri
 #pragma unroll
             for (int c = 0; c < 8; ++c) *(v4f*)(T + (4 * c + q) * kTLd + 4 * c16) = cur[c];
             lds_wave_sync();
+            // both 16-column halves of the step at once, so the two dependent
+            // MFMA chains interleave
+            v4f tl[2][4];
+#pragma unroll
+            for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+                for (int sg = 0; sg < 4; ++sg) tl[kt][sg] = *(const v4f*)(T + (kt * 16 + c16) * kTLd + 16 * q + 4 * sg);
             v4f accL[2][NRT];
 #pragma unroll
-            for (int kt = 0; kt < 2; ++kt) {
-                v4f tl[4];
+            for (int kt = 0; kt < 2; ++kt)
 #pragma unroll
-                for (int sg = 0; sg < 4; ++sg) tl[sg] = *(const v4f*)(T + (kt * 16 + c16) * kTLd + 16 * q + 4 * sg);
+                for (int rt = 0; rt < NRT; ++rt) accL[kt][rt] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int rt = 0; rt < NRT; ++rt) {
-                    v4f a = v4f{0.f, 0.f, 0.f, 0.f};
+            for (int s = 0; s < 16; ++s)
 #pragma unroll
-                    for (int s = 0; s < 16; ++s)
-                        a = __builtin_amdgcn_mfma_f32_16x16x4f32(tl[s >> 2][s & 3], krl[rt][s], a, 0, 0, 0);
-                    accL[kt][rt] = a;
-                }
-            }
+                for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+                    for (int rt = 0; rt < NRT; ++rt)
+                        accL[kt][rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(tl[kt][s >> 2][s & 3], krl[rt][s],
+                                                                           accL[kt][rt], 0, 0, 0);
             // this wave's partial: lane holds columns k0 + kt*16 + 4q + v, rank rt*16 + c16
 #pragma unroll
             for (int kt = 0; kt < 2; ++kt)
 #pragma unroll
                 for (int rt = 0; rt < NRT; ++rt) sRed[buf][((w * 2 + kt) * NRT + rt) * 64 + l] = accL[kt][rt];
             lds_block_sync();
+            // P_L partial stores of this block row over the step's columns (past K: dropped)
+            const int64_t k0 = step_col(st);
+            const auto lrs = buf_rsrc(PLpart + ((int64_t)blockIdx.x * K + k0) * ld,
+                                      (uint32_t)(max((int64_t)0, min((int64_t)kStep, K - k0)) * ld * 4));
             // sum the four waves and write this block row's partial of P_L: every
             // thread stores 2*NRT values (uniform count, so the wait for the next
             // step's Y loads stays exact)
@@ -264,19 +282,19 @@ __global__ __launch_bounds__(256) void k_contract_mfma_f32(const float* __restri
                     s1 += e[1];
                 }
                 const int r = rt * 16 + (lane & 15);
-                const uint32_t off = r < ld
-                    ? (uint32_t)(((st * kStep + kt * 16 + 4 * (lane >> 4) + v0) * ld + r) * 4) : kOOB;
+                const uint32_t off = r < ld ? (uint32_t)(((kt * 16 + 4 * (lane >> 4) + v0) * ld + r) * 4) : kOOB;
                 __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(s0), lrs, (int)off, 0, 0);
                 __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(s1), lrs, (int)(off + (uint32_t)(ld * 4)), 0, 0);
             }
         }
     };
 
-    // three register buffers rotate through the unrolled loop (no copies, so
-    // the loads of the two steps ahead stay in flight)
-    v4f b0[8], b1[8], b2[8];
-    load_step(b0, 0);
-    load_step(b1, 1);
+    // kDepth + 1 register buffers rotate through the unrolled loop (no copies,
+    // so the loads of the kDepth steps ahead stay in flight)
+    constexpr int NB = kDepth + 1;
+    v4f buf[NB][8];
+#pragma unroll
+    for (int d = 0; d < kDepth; ++d) load_step(buf[d], d);
     if (DO_R) {
         store_krr(krt, 0);
         for (int base = kKrBatch * 256; base < n4; base += kKrBatch * 256) {  // wide chunks only
@@ -285,10 +303,10 @@ __global__ __launch_bounds__(256) void k_contract_mfma_f32(const float* __restri
         }
     }
     lds_block_sync();
-    for (int64_t st = 0; st < nsteps; st += 3) {
-        step(b0, b2, st);
-        if (st + 1 < nsteps) step(b1, b0, st + 1);
-        if (st + 2 < nsteps) step(b2, b1, st + 2);
+    for (int64_t st = 0; st < nsteps; st += NB) {
+#pragma unroll
+        for (int ph = 0; ph < NB; ++ph)
+            if (ph == 0 || st + ph < nsteps) step(buf[ph], buf[(ph + kDepth) % NB], st + ph);
     }
 
     if (DO_R) {
