@@ -7,6 +7,7 @@
 #include <stddef.h>
 
 #include "cpgrad.h"
+#include "cpg_fastdiv.h"
 
 struct cpmlp_s;
 
@@ -75,22 +76,22 @@ struct Tiling {
 hipError_t launch_contract_valu(int ydt, int fdt, const void* Y, int64_t J, int64_t K,
                                 const void* facset, int nstar, const Tiling& t, int roles, int ld,
                                 void* PRpart, void* PLpart, hipStream_t stream);
-// Buffers of the MFMA contractions: the Khatri-Rao tables they read and the
-// split partials they write.
+// What a kernel needs to generate Khatri-Rao rows (eq. 3.3) itself: the
+// float32 factors, the mode sizes as multiply-shift divisors, R and n*.
+struct KrGen {
+    const float* A[CPG_MAX_MODES];
+    FastDiv fd[CPG_MAX_MODES];
+    int N;
+    int R;
+    int nstar;
+};
+// Buffers of the MFMA contractions: the split partials they write.
 struct MfmaBufs {
     float* PRpart;
     float* PLpart;
-    int ld;             // row stride (padded rank) of the partials and tables
-    const float* KRL;   // J x ld rows of the product over modes 1..n*
-    const float* KRR;   // K x ld rows of the product over modes n*+1..N
+    int ld;             // row stride (padded rank) of the partials
+    KrGen kg;           // factors for the Khatri-Rao rows
 };
-// Khatri-Rao tables (zero in columns R..ld-1) from the factor set: float32
-// KRL (J x ld, modes 1..n*) and KRR (K x ld, modes n*+1..N) for the MFMA
-// contractions, and float64 KRsR (J_{n*-1} x ld, modes 1..n*-1) and KRsL
-// (K_{n*+1} x ld, modes n*+2..N) for the first-mode gradients.  A null
-// table is skipped.
-hipError_t launch_kr_tables(const FacSet<float>& fs, int nstar, int64_t J, int64_t K, int ld, float* KRL,
-                            float* KRR, double* KRsR, int64_t TsR, double* KRsL, int64_t TsL, hipStream_t stream);
 hipError_t launch_contract_mfma(int ydt, int mode, const void* Y, int64_t J, int64_t K, const Tiling& t,
                                 int roles, const MfmaBufs& bufs, hipStream_t stream);
 hipError_t launch_contract_bf16(int ydt, int mode, const void* Y, int64_t J, int64_t K,
@@ -109,11 +110,12 @@ struct ReduceFirst {
     int side;             // 0 = right: rows t + T*i;  1 = left: rows i + I*t
     int64_t I;            // rows of the gradient (I_n of the side's first mode)
     int64_t T;            // terms per gradient entry (J_{n-1} right, K_n left)
-    const double* KRs;    // T x ld float64 Khatri-Rao rows of the side's remaining modes
+    int kr_first;         // the side's remaining modes (0-based), whose Khatri-Rao rows weight the terms
+    int kr_count;
     float* Z;             // rows x ld reduced chain tensor (out)
     float* G;             // I x R gradient (out)
 };
-hipError_t launch_reduce_first(const ReduceFirst* sides, int nsides, const FacSet<float>& fs, double* grams,
+hipError_t launch_reduce_first(const ReduceFirst* sides, int nsides, const KrGen& kg, double* grams,
                                hipStream_t stream);
 
 // First chain step of one side for the all-mode gradient (float32, many blocks).

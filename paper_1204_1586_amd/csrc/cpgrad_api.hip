@@ -36,10 +36,7 @@ struct cpgrad_plan_s {
     void* chain[4] = {nullptr, nullptr, nullptr, nullptr};
     void* PRpart = nullptr;
     void* PLpart = nullptr;
-    float* KRL = nullptr;     // Khatri-Rao tables of the MFMA contractions (J x ld, K x ld)
-    float* KRR = nullptr;
-    double* KRsR = nullptr;   // float64 tables of the first gradients (J_{n*-1} x ld, K_{n*+1} x ld)
-    double* KRsL = nullptr;
+    FastDiv fd[CPG_MAX_MODES];  // mode sizes as multiply-shift divisors (kernels unravel row indices)
     bool fused_first = false; // partial reduction fused with each side's first gradient
     void* Gtmp = nullptr;
     double* grams = nullptr;
@@ -178,12 +175,8 @@ static int configure(cpgrad_plan_s* p) {
     const size_t oC3 = off;     off += al(chain_rows * R * a);
     const size_t oPRp = off;    off += al(nkc * p->J * R * a);
     const size_t oPLp = off;    off += al(njr * p->K * R * a);
-    const bool tables = p->t_fused.kernel == 2 || p->t_right.kernel == 2 || p->t_left.kernel == 2;
-    const size_t oKL = off;     off += tables ? al(p->J * R * 4) : 0;
-    const size_t oKR = off;     off += tables ? al(p->K * R * 4) : 0;
     p->fused_first = fused_first_ok(p);
-    const size_t oKsR = off;    off += p->fused_first ? al(p->Jn[p->nstar - 1] * R * 8) : 0;
-    const size_t oKsL = off;    off += p->fused_first ? al(p->Kn[p->nstar + 1] * R * 8) : 0;
+    for (int n = 0; n < N; ++n) p->fd[n] = make_fastdiv((uint32_t)p->dims[n]);
     const size_t oG = off;      off += al(maxI * R * a);
     const size_t oGr = off;     off += al((size_t)N * p->R * p->R * 8);
     const size_t oS = off;      off += al(16 * 8);
@@ -208,10 +201,6 @@ static int configure(cpgrad_plan_s* p) {
     p->chain[3] = b + oC3;
     p->PRpart = b + oPRp;
     p->PLpart = b + oPLp;
-    p->KRL = tables ? (float*)(b + oKL) : nullptr;
-    p->KRR = tables ? (float*)(b + oKR) : nullptr;
-    p->KRsR = p->fused_first ? (double*)(b + oKsR) : nullptr;
-    p->KRsL = p->fused_first ? (double*)(b + oKsL) : nullptr;
     p->Gtmp = b + oG;
     p->grams = (double*)(b + oGr);
     p->scal = (double*)(b + oS);
@@ -252,11 +241,23 @@ static AnyFacSet facsets(const cpgrad_plan_s* p, const void* const* A) {
     return s;
 }
 
+static KrGen kr_gen(const cpgrad_plan_s* p, const FacSet<float>& fs) {
+    KrGen g{};
+    for (int n = 0; n < p->N; ++n) {
+        g.A[n] = fs.A[n];
+        g.fd[n] = p->fd[n];
+    }
+    g.N = p->N;
+    g.R = p->R;
+    g.nstar = p->nstar;
+    return g;
+}
+
 static hipError_t launch_contract(cpgrad_plan_s* p, const void* Y, const AnyFacSet& fs, const Tiling& t,
                                   int roles) {
     if (t.n_kc > 65535) return hipErrorInvalidConfiguration;
     if (t.kernel == 2 || t.kernel == 3) {
-        MfmaBufs o{(float*)p->PRpart, (float*)p->PLpart, p->ld, p->KRL, p->KRR};
+        MfmaBufs o{(float*)p->PRpart, (float*)p->PLpart, p->ld, kr_gen(p, fs.f)};
         if (t.kernel == 3)
             return launch_contract_bf16(p->ydt, p->mode, Y, p->J, p->K, fs.f, p->nstar, t, roles, o, p->stream);
         return launch_contract_mfma(p->ydt, p->mode, Y, p->J, p->K, t, roles, o, p->stream);
@@ -268,15 +269,6 @@ static hipError_t launch_contract(cpgrad_plan_s* p, const void* Y, const AnyFacS
 // Launch one big contraction; with profiling on, bracket it with HIP events
 // recorded on the plan's stream.
 static hipError_t run_contract(cpgrad_plan_s* p, const void* Y, const AnyFacSet& fs, const Tiling& t, int roles) {
-    if (t.kernel == 2 || t.kernel == 3) {
-        // Khatri-Rao tables first (outside the timed bracket: a kernel of its own)
-        const bool big = t.kernel == 2;
-        hipError_t e = launch_kr_tables(fs.f, p->nstar, p->J, p->K, p->ld, big && (roles & 2) ? p->KRL : nullptr,
-                                        big && (roles & 1) ? p->KRR : nullptr, (roles & 1) ? p->KRsR : nullptr,
-                                        p->Jn[p->nstar - 1], (roles & 2) ? p->KRsL : nullptr, p->Kn[p->nstar + 1],
-                                        p->stream);
-        if (e != hipSuccess) return e;
-    }
     if (!p->profile) return launch_contract(p, Y, fs, t, roles);
     if (p->ev_used == p->ev_start.size()) {
         if (p->ev_used >= 65536) return launch_contract(p, Y, fs, t, roles);  // pool full: stop recording
@@ -318,11 +310,12 @@ static int finish_partials(cpgrad_plan_s* p, const FacSet<float>* fs, const Tili
         int ns = 0;
         if (fr)
             sd[ns++] = ReduceFirst{(const float*)p->PRpart, t.n_kc, p->J, p->ld, 0, p->dims[p->nstar - 1],
-                                   p->Jn[p->nstar - 1], p->KRsR, (float*)p->PR, (float*)Gr};
+                                   p->Jn[p->nstar - 1], 0, p->nstar - 1, (float*)p->PR, (float*)Gr};
         if (fl)
             sd[ns++] = ReduceFirst{(const float*)p->PLpart, t.n_jr, p->K, p->ld, 1, p->dims[p->nstar],
-                                   p->Kn[p->nstar + 1], p->KRsL, (float*)p->PL, (float*)Gl};
-        CPG_TRY(launch_reduce_first(sd, ns, *fs, grams ? p->grams : nullptr, p->stream));
+                                   p->Kn[p->nstar + 1], p->nstar + 1, p->N - p->nstar - 1, (float*)p->PL,
+                                   (float*)Gl};
+        CPG_TRY(launch_reduce_first(sd, ns, kr_gen(p, *fs), grams ? p->grams : nullptr, p->stream));
     }
     if ((roles & 1) && !fr) CPG_TRY(launch_reduce_parts(p->fdt, p->PRpart, t.n_kc, p->J, p->ld, p->PR, p->stream));
     if ((roles & 2) && !fl) CPG_TRY(launch_reduce_parts(p->fdt, p->PLpart, t.n_jr, p->K, p->ld, p->PL, p->stream));

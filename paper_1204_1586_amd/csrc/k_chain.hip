@@ -68,12 +68,14 @@ hipError_t launch_reduce_parts(int fdt, const void* parts, int64_t nparts, int64
 // float32, and forms from the stored values
 //   right (eq. 3.12): G(i, r) = sum_t Z(t + T i, r) KRs(t, r),  T = J_{n-1}
 //   left  (eq. 3.16): G(i, r) = sum_t Z(i + I t, r) KRs(t, r),  T = K_n
-// with KRs the float64 Khatri-Rao rows of the side's remaining modes.  Extra
-// blocks (one per mode) compute the float64 Grams when `grams` is set.
+// with KRs the float64 Khatri-Rao rows of the side's remaining modes, formed
+// from the factors in place.  Extra blocks (one per mode) compute the float64
+// Grams when `grams` is set.
 // ---------------------------------------------------------------------------
 constexpr int kRfBatch = 16;   // partial loads in flight per thread
 
-__device__ __forceinline__ void reduce_first_rows(const ReduceFirst& a, int64_t i, int R, d4s* spart) {
+__device__ __forceinline__ void reduce_first_rows(const ReduceFirst& a, int64_t i, const KrGen& kg, d4s* spart) {
+    const int R = kg.R;
     const int tid = threadIdx.x;
     const int ld = a.ld;
     const int nq = ld >> 2;                 // float4 columns of a row
@@ -89,6 +91,22 @@ __device__ __forceinline__ void reduce_first_rows(const ReduceFirst& a, int64_t 
     if (q < nq) {
         for (int64_t t = tslot; t < a.T; t += tstep) {
             const int64_t row = rbase + t * rstride;
+            // weights: float64 Khatri-Rao row t of modes kr_first.. (Notation 2.1 order), zero past R
+            double w[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) w[u] = 4 * q + u < R ? 1.0 : 0.0;
+            uint32_t idx = (uint32_t)t;
+            for (int m = a.kr_first; m < a.kr_first + a.kr_count; ++m) {
+                const FastDiv f = kg.fd[m];
+                const uint32_t qd = fast_div(idx, f);
+                const float* Am = kg.A[m] + (int64_t)(idx - qd * f.d) * R;
+                idx = qd;
+                float x[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) x[u] = Am[min(4 * q + u, R - 1)];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) w[u] *= (double)x[u];
+            }
             const float* src = a.parts + row * ld + 4 * q;
             d4s acc{0.0, 0.0, 0.0, 0.0};
             auto add = [&](const float4& v) {
@@ -109,7 +127,6 @@ __device__ __forceinline__ void reduce_first_rows(const ReduceFirst& a, int64_t 
             for (; p < a.nparts; ++p) add(*(const float4*)(src + p * pstride));
             const float4 z{(float)acc.x, (float)acc.y, (float)acc.z, (float)acc.w};
             *(float4*)(a.Z + row * ld + 4 * q) = z;
-            const double* w = a.KRs + t * ld + 4 * q;
             g.x += (double)z.x * w[0];
             g.y += (double)z.y * w[1];
             g.z += (double)z.z * w[2];
@@ -137,20 +154,20 @@ __device__ __forceinline__ void reduce_first_rows(const ReduceFirst& a, int64_t 
 }
 
 __global__ __launch_bounds__(256) void k_reduce_first(ReduceFirst s0, ReduceFirst s1, int64_t nb0, int64_t nb1,
-                                                      FacSet<float> fs, double* __restrict__ grams) {
+                                                      KrGen kg, double* __restrict__ grams) {
     __shared__ d4s spart[256];
     const int64_t b = blockIdx.x;
     if (b < nb0) {
-        reduce_first_rows(s0, b, fs.R, spart);
+        reduce_first_rows(s0, b, kg, spart);
     } else if (b < nb0 + nb1) {
-        reduce_first_rows(s1, b - nb0, fs.R, spart);
+        reduce_first_rows(s1, b - nb0, kg, spart);
     } else {
         // float64 Gram of mode m, terms in index order
         const int m = (int)(b - nb0 - nb1);
-        if (grams == nullptr || m >= fs.N) return;
-        const int R = fs.R;
-        const float* A = fs.A[m];
-        const int64_t I = fs.dims[m];
+        if (grams == nullptr || m >= kg.N) return;
+        const int R = kg.R;
+        const float* A = kg.A[m];
+        const int64_t I = kg.fd[m].d;
         for (int e = threadIdx.x; e < R * R; e += 256) {
             const int r = e / R, c = e - (e / R) * R;
             double acc = 0.0;
@@ -171,15 +188,15 @@ __global__ __launch_bounds__(256) void k_reduce_first(ReduceFirst s0, ReduceFirs
     }
 }
 
-hipError_t launch_reduce_first(const ReduceFirst* sides, int nsides, const FacSet<float>& fs, double* grams,
+hipError_t launch_reduce_first(const ReduceFirst* sides, int nsides, const KrGen& kg, double* grams,
                                hipStream_t s) {
     if (nsides < 1 || nsides > 2) return hipErrorInvalidValue;
     for (int k = 0; k < nsides; ++k)
         if ((sides[k].ld & 3) != 0 || sides[k].ld > 64) return hipErrorInvalidValue;
     const int64_t nb0 = sides[0].I, nb1 = nsides > 1 ? sides[1].I : 0;
-    const int64_t nb = nb0 + nb1 + (grams ? fs.N : 0);
+    const int64_t nb = nb0 + nb1 + (grams ? kg.N : 0);
     hipLaunchKernelGGL(k_reduce_first, dim3((unsigned)nb), dim3(256), 0, s, sides[0], sides[nsides - 1], nb0, nb1,
-                       fs, grams);
+                       kg, grams);
     return hipGetLastError();
 }
 

@@ -12,13 +12,15 @@
 // reduces over rows, so each wave transposes its own 64 x 32 sub-tile
 // through a private LDS region and runs 16x16x4 MFMAs with the columns as
 // output rows; the four waves' partial sums meet in LDS and one partial row
-// block of P_L is written per step.  The KR_R rows of the block's whole column
-// chunk are built once into LDS before the loop and KR_L rows of the block
-// once into registers, so the only global loads inside the loop are the Y
-// loads of the next step, which stay in flight across the step's MFMAs.
+// block of P_L is written per step.  The KR_R rows of all of the block's
+// column steps are generated once into LDS before the loop and the KR_L rows
+// of the block once into registers, so the only global loads inside the loop
+// are the Y loads of the steps ahead, which stay in flight across the step's
+// MFMAs.  Steps of 32 columns are dealt round-robin over the block columns.
 // Partials go to PRpart[block column][J][R] and PLpart[block row][K][R],
 // reduced later in a fixed order.
 #include "cpg_device.h"
+#include "cpg_fastdiv.h"
 
 #include <algorithm>
 
@@ -31,17 +33,6 @@ constexpr int kStep = 32;       // columns of Y per step
 constexpr int kTLd = 68;        // LDS leading dimension of the transposed sub-tile
 constexpr int kDepth = 2;       // steps of Y loads in flight ahead of the MFMAs
 
-__device__ __forceinline__ float kr_prod(const FacSet<float>& fs, int first, int count, int64_t idx, int r) {
-    float v = 1.f;
-    for (int m = 0; m < count; ++m) {
-        const int64_t d = fs.dims[first + m];
-        const int64_t q = idx / d;
-        const int64_t i = idx - q * d;
-        idx = q;
-        v *= fs.A[first + m][i * fs.R + r];
-    }
-    return v;
-}
 
 __device__ __forceinline__ void lds_wave_sync() {
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
@@ -54,66 +45,9 @@ __device__ __forceinline__ void lds_block_sync() {
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
-// Khatri-Rao tables (eq. 3.3, Notation 2.1), one thread per entry, zero in the
-// padding columns R..ld-1: float32 KRL (J x ld, product over modes 1..n*) and
-// KRR (K x ld, modes n*+1..N) read by the contractions; float64 KRsR
-// (J_{n*-1} x ld, modes 1..n*-1) and KRsL (K_{n*+1} x ld, modes n*+2..N)
-// weighting the first gradient of each side.  Entry ranges of the grid, in
-// order: KRL, KRR, KRsR, KRsL (a null table has no range).
-__global__ __launch_bounds__(256) void k_kr_tables(FacSet<float> fs, int nstar, int64_t J, int64_t K, int ld,
-                                                   float* __restrict__ KRL, float* __restrict__ KRR,
-                                                   double* __restrict__ KRsR, int64_t TsR,
-                                                   double* __restrict__ KRsL, int64_t TsL) {
-    int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int N = fs.N;
-    const int64_t nL = KRL ? J * ld : 0, nR = KRR ? K * ld : 0;
-    const int64_t nsR = KRsR ? TsR * ld : 0, nsL = KRsL ? TsL * ld : 0;
-    if (e < nL + nR) {
-        const bool left = e < nL;
-        const int64_t f = left ? e : e - nL;
-        const int64_t row = f / ld;
-        const int r = (int)(f - row * ld);
-        float v = 0.f;
-        if (r < fs.R) v = left ? kr_prod(fs, 0, nstar, row, r) : kr_prod(fs, nstar, N - nstar, row, r);
-        (left ? KRL : KRR)[f] = v;
-        return;
-    }
-    e -= nL + nR;
-    if (e >= nsR + nsL) return;
-    const bool right = e < nsR;
-    const int64_t f = right ? e : e - nsR;
-    int64_t idx = f / ld;
-    const int r = (int)(f - idx * ld);
-    const int first = right ? 0 : nstar + 1;
-    const int count = right ? nstar - 1 : N - nstar - 1;
-    double v = 0.0;
-    if (r < fs.R) {
-        v = 1.0;
-        for (int m = 0; m < count; ++m) {
-            const int64_t d = fs.dims[first + m];
-            const int64_t qd = idx / d;
-            v *= (double)fs.A[first + m][(idx - qd * d) * fs.R + r];
-            idx = qd;
-        }
-    }
-    (right ? KRsR : KRsL)[f] = v;
-}
-
-hipError_t launch_kr_tables(const FacSet<float>& fs, int nstar, int64_t J, int64_t K, int ld, float* KRL, float* KRR,
-                            double* KRsR, int64_t TsR, double* KRsL, int64_t TsL, hipStream_t stream) {
-    const int64_t total = ((KRL ? J : 0) + (KRR ? K : 0) + (KRsR ? TsR : 0) + (KRsL ? TsL : 0)) * ld;
-    if (total == 0) return hipSuccess;
-    const int64_t blocks = (total + 255) / 256;
-    if (blocks > INT32_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_kr_tables, dim3((unsigned)blocks), dim3(256), 0, stream, fs, nstar, J, K, ld, KRL, KRR, KRsR,
-                       TsR, KRsL, TsL);
-    return hipGetLastError();
-}
-
 template <int NRT, bool DO_R, bool DO_L>
 __global__ __launch_bounds__(256) void k_contract_mfma_f32(const float* __restrict__ Y, int64_t J, int64_t K,
-                                                            int64_t kcols, int ld, const float* __restrict__ KRL,
-                                                            const float* __restrict__ KRR,
+                                                            int64_t kcols, int ld, KrGen kg,
                                                             float* __restrict__ PRpart, float* __restrict__ PLpart) {
     constexpr int RT = NRT * 16;
     constexpr int KRLD = RT + 4;  // LDS row stride of the KR_R tile
@@ -139,38 +73,132 @@ __global__ __launch_bounds__(256) void k_contract_mfma_f32(const float* __restri
     const int64_t nsteps = (gsteps - blockIdx.y + n_kc - 1) / n_kc;
     auto step_col = [&](int64_t st) { return (st * n_kc + blockIdx.y) * kStep; };   // first column of step st
 
-    // Prologue.  Table loads go first and the first two steps of Y after them,
-    // so waiting for the tables leaves the Y loads in flight.  All loads are
-    // buffer loads without branches (rows or columns outside read as zero),
-    // which keeps the compiler's count of loads in flight exact.
+    // Prologue.  The first steps of Y are issued first; meanwhile the block's
+    // Khatri-Rao rows (eq. 3.3, Notation 2.1 order: the first mode of a
+    // product fastest) are generated from the factors: row indices unravel
+    // into per-mode indices by multiply-shift division, one round of factor
+    // loads per mode; factor entries past R read as zero (buffer loads, no
+    // branches).  Products are formed in float32 in mode order.
+    const int R = kg.R;
+    auto fac_rsrc = [&](int m) { return buf_rsrc(kg.A[m], (uint32_t)(kg.fd[m].d * (uint32_t)R * 4)); };
     //
     // KR_L operand of the left contraction: rows jw + 16q + s, columns rt*16 + c16
     float krl[DO_L ? NRT : 1][16];
-    if (DO_L) {
-        const auto lrs_tab = buf_rsrc(KRL + jb * ld, (uint32_t)(min((int64_t)kMfmaRows, J - jb) * ld * 4));
-#pragma unroll
-        for (int rt = 0; rt < NRT; ++rt) {
-            const int r = rt * 16 + c16;
-#pragma unroll
-            for (int s = 0; s < 16; ++s) {
-                const uint32_t off = r < ld ? (uint32_t)(((64 * w + 16 * q + s) * ld + r) * 4) : kOOB;
-                krl[rt][s] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(lrs_tab, (int)off, 0, 0));
-            }
-        }
-    }
     // KR_R rows of the block's steps (LDS row st*32 + kk <- column step_col(st) + kk),
-    // four ranks per float4 (ld is a multiple of 4); rows past K read as zero
+    // four ranks per entry; rows past K and ranks past R are zero
     constexpr int kKrBatch = 8;
     const int n4 = (int)(nsteps * kStep) * (RT / 4);
-    const auto rrs_tab = buf_rsrc(KRR, (uint32_t)(K * ld * 4));
     auto load_krr = [&](v4f (&t)[kKrBatch], int base) {
+        uint32_t idx[kKrBatch];
+        int r4[kKrBatch];
 #pragma unroll
         for (int u = 0; u < kKrBatch; ++u) {
             const int e = base + u * 256 + tid;
-            const int kk = e / (RT / 4), r4 = (e - kk * (RT / 4)) * 4;
+            const int kk = e / (RT / 4);
+            r4[u] = (e - kk * (RT / 4)) * 4;
             const int64_t k = step_col(kk / kStep) + (kk & (kStep - 1));
-            const uint32_t off = (e < n4 && r4 < ld && k < K) ? (uint32_t)((k * ld + r4) * 4) : kOOB;
-            t[u] = __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(rrs_tab, (int)off, 0, 0));
+            const bool ok = e < n4 && k < K;
+            idx[u] = ok ? (uint32_t)k : 0u;
+            const float one = ok ? 1.f : 0.f;
+            t[u] = v4f{one, one, one, one};
+        }
+        for (int m = kg.nstar; m < kg.N; ++m) {
+            const FastDiv f = kg.fd[m];
+            const auto rs = fac_rsrc(m);
+#pragma unroll
+            for (int u = 0; u < kKrBatch; ++u) {
+                const uint32_t qd = fast_div(idx[u], f);
+                const uint32_t i = idx[u] - qd * f.d;
+                idx[u] = qd;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int r = r4[u] + c;
+                    const uint32_t off = r < R ? (i * (uint32_t)R + (uint32_t)r) * 4 : kOOB;
+                    t[u][c] *= __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0));
+                }
+            }
+        }
+    };
+    // First batch of KR_R rows and the KR_L rows together: round j loads mode j
+    // of the left product and mode n*+j of the right one, so the rounds are
+    // max(n*, N-n*) (a mode past a side's count multiplies by one).
+    auto gen_first = [&](v4f (&t)[kKrBatch]) {
+        uint32_t idxL[16], idxR[kKrBatch];
+        int r4[kKrBatch];
+        if (DO_L) {
+#pragma unroll
+            for (int s = 0; s < 16; ++s) {
+                const int64_t j = jw + 16 * q + s;
+                idxL[s] = j < J ? (uint32_t)j : 0u;
+#pragma unroll
+                for (int rt = 0; rt < NRT; ++rt) krl[rt][s] = j < J ? 1.f : 0.f;
+            }
+        }
+        if (DO_R) {
+#pragma unroll
+            for (int u = 0; u < kKrBatch; ++u) {
+                const int e = u * 256 + tid;
+                const int kk = e / (RT / 4);
+                r4[u] = (e - kk * (RT / 4)) * 4;
+                const int64_t k = step_col(kk / kStep) + (kk & (kStep - 1));
+                const bool ok = e < n4 && k < K;
+                idxR[u] = ok ? (uint32_t)k : 0u;
+                const float one = ok ? 1.f : 0.f;
+                t[u] = v4f{one, one, one, one};
+            }
+        }
+        const int nL = DO_L ? kg.nstar : 0;
+        const int nR = DO_R ? kg.N - kg.nstar : 0;
+        const int rounds = nL > nR ? nL : nR;
+        for (int j = 0; j < rounds; ++j) {
+            const bool aL = j < nL, aR = j < nR;
+            float vl[DO_L ? NRT : 1][16], vr[DO_R ? kKrBatch : 1][4];
+            if (DO_L) {
+                const int m = aL ? j : 0;
+                const FastDiv f = kg.fd[m];
+                const auto rs = fac_rsrc(m);
+#pragma unroll
+                for (int s = 0; s < 16; ++s) {
+                    const uint32_t qd = fast_div(idxL[s], f);
+                    const uint32_t i = idxL[s] - qd * f.d;
+                    idxL[s] = qd;
+#pragma unroll
+                    for (int rt = 0; rt < NRT; ++rt) {
+                        const int r = rt * 16 + c16;
+                        const uint32_t off = (aL && r < R) ? (i * (uint32_t)R + (uint32_t)r) * 4 : kOOB;
+                        vl[rt][s] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0));
+                    }
+                }
+            }
+            if (DO_R) {
+                const int m = kg.nstar + (aR ? j : 0);
+                const FastDiv f = kg.fd[m];
+                const auto rs = fac_rsrc(m);
+#pragma unroll
+                for (int u = 0; u < kKrBatch; ++u) {
+                    const uint32_t qd = fast_div(idxR[u], f);
+                    const uint32_t i = idxR[u] - qd * f.d;
+                    idxR[u] = qd;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const int r = r4[u] + c;
+                        const uint32_t off = (aR && r < R) ? (i * (uint32_t)R + (uint32_t)r) * 4 : kOOB;
+                        vr[u][c] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0));
+                    }
+                }
+            }
+            if (DO_L) {
+#pragma unroll
+                for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+                    for (int s = 0; s < 16; ++s) krl[rt][s] *= aL ? vl[rt][s] : 1.f;
+            }
+            if (DO_R) {
+#pragma unroll
+                for (int u = 0; u < kKrBatch; ++u)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) t[u][c] *= aR ? vr[u][c] : 1.f;
+            }
         }
     };
     auto store_krr = [&](const v4f (&t)[kKrBatch], int base) {
@@ -181,8 +209,6 @@ __global__ __launch_bounds__(256) void k_contract_mfma_f32(const float* __restri
             if (e < n4) *(v4f*)(sKRR + kk * KRLD + r4) = t[u];
         }
     };
-    v4f krt[kKrBatch];
-    if (DO_R) load_krr(krt, 0);
 
     // Y loads: lane (q, c16), slot c -> rows jw + 4*c16 .. +3 of column
     // step_col(st) + 4c + q, through a buffer resource over the step's 32
@@ -295,9 +321,11 @@ __global__ __launch_bounds__(256) void k_contract_mfma_f32(const float* __restri
     v4f buf[NB][8];
 #pragma unroll
     for (int d = 0; d < kDepth; ++d) load_step(buf[d], d);
-    if (DO_R) {
-        store_krr(krt, 0);
-        for (int base = kKrBatch * 256; base < n4; base += kKrBatch * 256) {  // wide chunks only
+    {
+        v4f krt[kKrBatch];
+        gen_first(krt);
+        if (DO_R) store_krr(krt, 0);
+        for (int base = kKrBatch * 256; DO_R && base < n4; base += kKrBatch * 256) {  // wide chunks only
             load_krr(krt, base);
             store_krr(krt, base);
         }
@@ -362,7 +390,7 @@ static hipError_t launch_one(dim3 grid, const float* Y, int64_t J, int64_t K, in
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL(kern, grid, dim3(256), dyn, s, Y, J, K, kcols, o.ld, o.KRL, o.KRR, o.PRpart, o.PLpart);
+    hipLaunchKernelGGL(kern, grid, dim3(256), dyn, s, Y, J, K, kcols, o.ld, o.kg, o.PRpart, o.PLpart);
     return hipGetLastError();
 }
 
