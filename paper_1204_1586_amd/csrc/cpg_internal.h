@@ -94,12 +94,12 @@ struct MfmaBufs {
 };
 hipError_t launch_contract_mfma(int ydt, int mode, const void* Y, int64_t J, int64_t K, const Tiling& t,
                                 int roles, const MfmaBufs& bufs, hipStream_t stream);
-hipError_t launch_contract_bf16(int ydt, int mode, const void* Y, int64_t J, int64_t K,
-                                const FacSet<float>& fs, int nstar, const Tiling& t, int roles,
-                                const MfmaBufs& bufs, hipStream_t stream);
+hipError_t launch_contract_bf16(int ydt, int mode, const void* Y, int64_t J, int64_t K, const Tiling& t,
+                                int roles, const MfmaBufs& bufs, hipStream_t stream);
 bool mfma_supported(int ydt, int fdt, int mode, int R);
-// widest column chunk (a multiple of 32) the float32 MFMA kernel holds in LDS
+// widest column chunk (a multiple of 32) the float32 / bf16 MFMA kernels hold in LDS
 int64_t mfma_f32_max_cols(int rt, int roles);
+int64_t mfma_bf16_max_cols(int rt, int roles, bool ylo, bool klo);
 
 // One side of the fused partial reduction + first-mode gradient (float32).
 struct ReduceFirst {

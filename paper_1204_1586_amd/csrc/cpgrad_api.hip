@@ -101,7 +101,7 @@ static Tiling tile_valu(int64_t J, int64_t K, int R, int fdt, int roles) {
 
 // Tiling of one pass for the MFMA kernel: 256-row blocks, column chunks of
 // whole 32-column steps, about two blocks per compute unit.
-static Tiling tile_mfma(int64_t J, int64_t K, int R, int roles, int kernel, int64_t cols) {
+static Tiling tile_mfma(int64_t J, int64_t K, int R, int roles, int kernel, int64_t cols, bool ylo, bool klo) {
     Tiling t{};
     t.kernel = kernel;
     t.rt = 16 * (int)cdiv(R, 16);
@@ -112,21 +112,18 @@ static Tiling tile_mfma(int64_t J, int64_t K, int R, int roles, int kernel, int6
     // steps sweep Y as one moving window (measured best for 64^4, rank 16)
     const int64_t target = 256;
     t.ktb = cols > 0 ? cdiv(cols, 32) : std::max<int64_t>(1, cdiv(steps * t.n_jr, target));
-    if (kernel == 2) {
-        // LDS holds the chunk's KR_R rows; a chunk of Y spans < 2^31 bytes (32-bit buffer offsets)
-        t.ktb = std::min<int64_t>(t.ktb, mfma_f32_max_cols(t.rt, roles) / 32);
-        t.ktb = std::max<int64_t>(1, std::min<int64_t>(t.ktb, ((int64_t(1) << 31) - 1) / (J * 4 * 32)));
-    }
+    // LDS holds the KR_R rows of a block's steps
+    if (kernel == 2) t.ktb = std::min<int64_t>(t.ktb, mfma_f32_max_cols(t.rt, roles) / 32);
+    if (kernel == 3) t.ktb = std::min<int64_t>(t.ktb, mfma_bf16_max_cols(t.rt, roles, ylo, klo) / 32);
+    t.ktb = std::max<int64_t>(1, t.ktb);
     t.n_kc = cdiv(steps, t.ktb);
     return t;
 }
 
 // 0 = generic kernel, 2 = float32 MFMA, 3 = bf16 MFMA (reduced-precision modes)
 static int mfma_kind(const cpgrad_plan_s* p) {
-    // 32-bit buffer offsets: a 32-column step of Y and the K x ld table stay below 2 GiB
-    if (p->kernel_opt == 1 || p->J * 4 * 32 >= (int64_t(1) << 31) ||
-        p->K * (4 * ((p->R + 3) / 4)) * 4 >= (int64_t(1) << 31))
-        return 0;
+    // 32-bit buffer offsets: a 32-column step of Y stays below 2 GiB
+    if (p->kernel_opt == 1 || p->J * 4 * 32 >= (int64_t(1) << 31)) return 0;
     if (p->mode == CPG_MODE_NATIVE)
         return (p->ydt == CPG_F32 && p->fdt == CPG_F32 && (p->J % 4) == 0) ? 2 : 0;
     return (p->fdt == CPG_F32 && (p->ydt == CPG_F32 || p->ydt == CPG_BF16) && (p->J % 8) == 0) ? 3 : 0;
@@ -134,7 +131,10 @@ static int mfma_kind(const cpgrad_plan_s* p) {
 
 static Tiling tile_pass(const cpgrad_plan_s* p, int roles) {
     const int kind = mfma_kind(p);
-    if (kind) return tile_mfma(p->J, p->K, p->R, roles, kind, p->opt_cols);
+    if (kind) {
+        const bool klo = p->mode == CPG_MODE_BF16_REFINED;
+        return tile_mfma(p->J, p->K, p->R, roles, kind, p->opt_cols, klo && p->ydt == CPG_F32, klo);
+    }
     return tile_valu(p->J, p->K, p->R, p->fdt, roles);
 }
 
@@ -259,7 +259,7 @@ static hipError_t launch_contract(cpgrad_plan_s* p, const void* Y, const AnyFacS
     if (t.kernel == 2 || t.kernel == 3) {
         MfmaBufs o{(float*)p->PRpart, (float*)p->PLpart, p->ld, kr_gen(p, fs.f)};
         if (t.kernel == 3)
-            return launch_contract_bf16(p->ydt, p->mode, Y, p->J, p->K, fs.f, p->nstar, t, roles, o, p->stream);
+            return launch_contract_bf16(p->ydt, p->mode, Y, p->J, p->K, t, roles, o, p->stream);
         return launch_contract_mfma(p->ydt, p->mode, Y, p->J, p->K, t, roles, o, p->stream);
     }
     return launch_contract_valu(p->ydt, p->fdt, Y, p->J, p->K, fs.ptr(p->fdt), p->nstar, t, roles, p->ld,

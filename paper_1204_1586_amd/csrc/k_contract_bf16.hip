@@ -9,17 +9,24 @@
 // refinement terms are formed in the same pass over Y, so the bytes moved do
 // not change.  bf16 keeps float32's exponent range, so no scaling is needed.
 //
-// Block = 4 waves x 64 rows of Y, steps of 32 columns.  Each lane loads, per
-// step, four chunks of 8 consecutive rows of one column (16 bytes of bf16 or
-// 32 bytes of float32).  A chunk is directly the 8-element operand of the
-// left contraction (reduction over rows, columns as output rows); the right
-// contraction reduces over columns, so each wave writes its 64 x 32 sub-tile
-// into a private LDS tile row-major and reads 8 consecutive columns of a row
-// per operand.  KR_R rows of the next step are built cooperatively in LDS
-// (split into hi / lo); KR_L rows of the block are built once into
-// registers.  Partials and the cross-wave reduction of the left product are
+// Block = 4 waves x 64 rows of Y, steps of 32 columns dealt round-robin over
+// the block columns (the grid sweeps Y as one moving window).  Each lane
+// loads, per step, four chunks of 8 consecutive rows of one column (16 bytes
+// of bf16 or 32 bytes of float32) through buffer loads that read zero past
+// the edges; two steps are in flight ahead of the MFMAs and the hi / lo split
+// of float32 data happens when a step is used.  A chunk is directly the
+// 8-element operand of the left contraction (reduction over rows, columns as
+// output rows); the right contraction reduces over columns, so each wave
+// writes its 64 x 32 sub-tile into a private LDS tile row-major and reads 8
+// consecutive columns of a row per operand.  The KR_R rows of all of the
+// block's steps are generated into LDS before the loop and the KR_L rows into
+// registers (split into hi / lo), from the factors by multiply-shift index
+// unravelling.  Partials and the cross-wave reduction of the left product are
 // as in the float32 MFMA kernel.
-#include "cpg_internal.h"
+#include "cpg_device.h"
+#include "cpg_fastdiv.h"
+
+#include <algorithm>
 
 namespace cpg {
 
@@ -29,8 +36,8 @@ typedef unsigned short v8us __attribute__((ext_vector_type(8)));
 
 constexpr int kB16Rows = 256;
 constexpr int kB16Step = 32;
-constexpr int kTrLd = 40;   // bf16 elements per row of the transposed LDS tile (80 bytes)
-constexpr int kKrLd = 40;   // bf16 elements per rank row of the KR_R tile
+constexpr int kB16Depth = 2;   // steps of Y loads in flight ahead of the MFMAs
+constexpr int kTrLd = 40;      // bf16 elements per row of the transposed LDS tile (80 bytes)
 
 // float -> bf16 bits, round to nearest even
 __device__ __forceinline__ unsigned short bf16_rne(float x) {
@@ -40,96 +47,91 @@ __device__ __forceinline__ unsigned short bf16_rne(float x) {
 }
 __device__ __forceinline__ float bf16_to_f(unsigned short b) { return __uint_as_float(((unsigned int)b) << 16); }
 
-__device__ __forceinline__ float kr_prod_f(const FacSet<float>& fs, int first, int count, int64_t idx, int r) {
-    float v = 1.f;
-    for (int m = 0; m < count; ++m) {
-        const int64_t d = fs.dims[first + m];
-        const int64_t q = idx / d;
-        const int64_t i = idx - q * d;
-        idx = q;
-        v *= fs.A[first + m][i * fs.R + r];
-    }
-    return v;
-}
-
 __device__ __forceinline__ void lds_wave_sync_b() {
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     __builtin_amdgcn_wave_barrier();
 }
+__device__ __forceinline__ void lds_block_sync_b() {
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
 
 __device__ __forceinline__ v8bf as_bf(v8us u) { return __builtin_bit_cast(v8bf, u); }
+
+// one step of Y as loaded: float32 storage (two float4 per chunk) or bf16 storage
+struct RawF {
+    v4f a[4], b[4];
+};
+struct RawB {
+    v8us c[4];
+};
+template <bool TYF>
+struct RawSel {
+    typedef RawF T;
+};
+template <>
+struct RawSel<false> {
+    typedef RawB T;
+};
+
+// LDS row stride (bf16 elements) of the KR_R tile for kcols columns
+__host__ __device__ constexpr int64_t krr_stride(int64_t kcols) { return kcols + 8; }
 
 // TYF: true if Y is stored as float32 (hi/lo split in registers), false for bf16 storage.
 template <bool TYF, int NRT, bool DO_R, bool DO_L, bool REFINE>
 __global__ __launch_bounds__(256) void k_contract_bf16(const void* __restrict__ Yv, int64_t J, int64_t K,
-                                                        FacSet<float> fs, int nstar, int64_t kcols, int ld,
-                                                        float* __restrict__ PRpart, float* __restrict__ PLpart) {
+                                                        int64_t kcols, int ld, KrGen kg, float* __restrict__ PRpart,
+                                                        float* __restrict__ PLpart) {
     constexpr int RT = NRT * 16;
     constexpr bool YLO = TYF && REFINE;   // a Y_lo term exists
     constexpr bool KLO = REFINE;          // a KR_lo term exists
-    __shared__ __attribute__((aligned(16))) unsigned short sKR[DO_R ? 2 : 1][KLO ? 2 : 1][DO_R ? RT * kKrLd : 8];
+    constexpr uint32_t ES = TYF ? 4 : 2;  // bytes per element of Y
+    typedef typename RawSel<TYF>::T Raw;
+    // dynamic LDS: KR_R hi (and lo) tiles [RT][krr_stride(kcols)] bf16
+    extern __shared__ __attribute__((aligned(16))) unsigned short sKRdyn[];
     __shared__ __attribute__((aligned(16))) unsigned short sTr[DO_R ? 4 : 1][YLO ? 2 : 1][DO_R ? 64 * kTrLd : 8];
     __shared__ v4f sRed[DO_L ? 2 : 1][DO_L ? 4 * 2 * NRT * 64 : 1];
+    const int KRS = (int)krr_stride(kcols);
+    unsigned short* sKRh = sKRdyn;
+    unsigned short* sKRl = sKRdyn + RT * KRS;
 
     const int tid = threadIdx.x;
     const int w = tid >> 6;
     const int l = tid & 63;
     const int q = l >> 4;
     const int c16 = l & 15;
-    const int R = fs.R;
-    const int N = fs.N;
+    const int R = kg.R;
     const int64_t jb = (int64_t)blockIdx.x * kB16Rows;
     const int64_t jw = jb + 64 * w;
-    const int64_t k_begin = (int64_t)blockIdx.y * kcols;
-    const int64_t k_end = min(K, k_begin + kcols);
-    const int64_t nsteps = (k_end - k_begin + kB16Step - 1) / kB16Step;
+    const int64_t n_kc = gridDim.y;
+    const int64_t gsteps = (K + kB16Step - 1) / kB16Step;
+    const int64_t nsteps = (gsteps - blockIdx.y + n_kc - 1) / n_kc;
+    auto step_col = [&](int64_t st) { return (st * n_kc + blockIdx.y) * kB16Step; };
+    auto fac_rsrc = [&](int m) { return buf_rsrc(kg.A[m], (uint32_t)(kg.fd[m].d * (uint32_t)R * 4)); };
 
-    // KR_L operand of the left product: rows jw + 32*jc + 8q + t, rank rt*16 + c16
-    v8us krl_hi[DO_L ? 2 : 1][DO_L ? NRT : 1], krl_lo[DO_L && KLO ? 2 : 1][DO_L && KLO ? NRT : 1];
-    if (DO_L) {
-#pragma unroll
-        for (int jc = 0; jc < 2; ++jc)
-#pragma unroll
-            for (int rt = 0; rt < NRT; ++rt) {
-                const int r = rt * 16 + c16;
-#pragma unroll
-                for (int t = 0; t < 8; ++t) {
-                    const int64_t j = jw + 32 * jc + 8 * q + t;
-                    const float v = (j < J && r < R) ? kr_prod_f(fs, 0, nstar, j, r) : 0.f;
-                    const unsigned short h = bf16_rne(v);
-                    krl_hi[jc][rt][t] = h;
-                    if (KLO) krl_lo[DO_L && KLO ? jc : 0][DO_L && KLO ? rt : 0][t] = bf16_rne(v - bf16_to_f(h));
-                }
-            }
-    }
-
-    auto build_krr = [&](int buf, int64_t k0) {
-        for (int e = tid; e < kB16Step * RT; e += 256) {
-            const int r = e / kB16Step, kk = e - (e / kB16Step) * kB16Step;
-            const int64_t k = k0 + kk;
-            const float v = (k < k_end && r < R) ? kr_prod_f(fs, nstar, N - nstar, k, r) : 0.f;
-            const unsigned short h = bf16_rne(v);
-            sKR[buf][0][r * kKrLd + kk] = h;
-            if (KLO) sKR[buf][KLO ? 1 : 0][r * kKrLd + kk] = bf16_rne(v - bf16_to_f(h));
-        }
-    };
-
-    // chunk s of a step: column k0 + 16*(s&1) + c16, rows jw + 32*(s>>1) + 8q .. +7
-    const int64_t rbase = jw + 8 * q;
-    auto load_step = [&](v8us* hi, v8us* lo, int64_t k0) {
+    // chunk s of a step: column step_col(st) + 16*(s&1) + c16, rows jw + 32*(s>>1) + 8q .. +7
+    auto load_step = [&](Raw& dst, int64_t st) {
+        const int64_t k0 = step_col(st);
+        const int64_t ncol = st < nsteps ? max((int64_t)0, min((int64_t)kB16Step, K - k0)) : 0;
+        const auto rs = buf_rsrc((const char*)Yv + (st < nsteps ? k0 : 0) * J * ES, (uint32_t)(ncol * J * ES));
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            const int64_t k = k0 + 16 * (s & 1) + c16;
-            const int64_t row = rbase + 32 * (s >> 1);
-            const bool ok = row < J && k < k_end;   // J % 8 == 0: a chunk is all in or all out
-            if (TYF) {
-                const float* Y = (const float*)Yv;
-                v4f a = v4f{0.f, 0.f, 0.f, 0.f}, b = a;
-                if (ok) {
-                    a = *(const v4f*)(Y + k * J + row);
-                    b = *(const v4f*)(Y + k * J + row + 4);
-                }
-                const float x[8] = {a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
+            const int64_t row = jw + 32 * (s >> 1) + 8 * q;   // J % 8 == 0: a chunk is all in or all out
+            const uint32_t off =
+                row < J ? (uint32_t)(((int64_t)(16 * (s & 1) + c16) * J + row) * ES) : kOOB;
+            if constexpr (TYF) {
+                dst.a[s] = __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0));
+                dst.b[s] = __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(off + 16), 0, 0));
+            } else {
+                dst.c[s] = __builtin_bit_cast(v8us, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)off, 0, 0));
+            }
+        }
+    };
+    auto split = [&](const Raw& r, v8us (&hi)[4], v8us (&lo)[4]) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            if constexpr (TYF) {
+                const float x[8] = {r.a[s][0], r.a[s][1], r.a[s][2], r.a[s][3],
+                                    r.b[s][0], r.b[s][1], r.b[s][2], r.b[s][3]};
 #pragma unroll
                 for (int t = 0; t < 8; ++t) {
                     const unsigned short h = bf16_rne(x[t]);
@@ -137,8 +139,124 @@ __global__ __launch_bounds__(256) void k_contract_bf16(const void* __restrict__ 
                     if (YLO) lo[s][t] = bf16_rne(x[t] - bf16_to_f(h));
                 }
             } else {
-                const unsigned short* Y = (const unsigned short*)Yv;
-                hi[s] = ok ? *(const v8us*)(Y + k * J + row) : v8us{0, 0, 0, 0, 0, 0, 0, 0};
+                hi[s] = r.c[s];
+            }
+        }
+    };
+
+    // Khatri-Rao rows (eq. 3.3, Notation 2.1 order), products in float32 in mode
+    // order, split into hi / lo.  KR_L: rows jw + 32*jc + 8q + t, rank rt*16 + c16.
+    // KR_R: LDS column st*32 + kk <- Y column step_col(st) + kk.  Round j loads
+    // mode j of the left product and mode n*+j of the right one.
+    v8us krl_hi[DO_L ? 2 : 1][DO_L ? NRT : 1], krl_lo[DO_L && KLO ? 2 : 1][DO_L && KLO ? NRT : 1];
+    constexpr int kKrBatch = 8;
+    const int n4 = (int)(nsteps * kB16Step) * (RT / 4);
+    auto gen_kr = [&](int base, bool with_left) {
+        float fl[DO_L ? NRT : 1][16];
+        uint32_t idxL[16], idxR[kKrBatch];
+        int r4[kKrBatch];
+        v4f t[kKrBatch];
+        if (DO_L && with_left) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int64_t j = jw + 32 * (e >> 3) + 8 * q + (e & 7);
+                idxL[e] = j < J ? (uint32_t)j : 0u;
+#pragma unroll
+                for (int rt = 0; rt < NRT; ++rt) fl[rt][e] = j < J ? 1.f : 0.f;
+            }
+        }
+        if (DO_R) {
+#pragma unroll
+            for (int u = 0; u < kKrBatch; ++u) {
+                const int e = base + u * 256 + tid;
+                const int kk = e / (RT / 4);
+                r4[u] = (e - kk * (RT / 4)) * 4;
+                const int64_t k = step_col(kk / kB16Step) + (kk & (kB16Step - 1));
+                const bool ok = e < n4 && k < K;
+                idxR[u] = ok ? (uint32_t)k : 0u;
+                const float one = ok ? 1.f : 0.f;
+                t[u] = v4f{one, one, one, one};
+            }
+        }
+        const int nL = (DO_L && with_left) ? kg.nstar : 0;
+        const int nR = DO_R ? kg.N - kg.nstar : 0;
+        const int rounds = nL > nR ? nL : nR;
+        for (int j = 0; j < rounds; ++j) {
+            const bool aL = j < nL, aR = j < nR;
+            float vl[DO_L ? NRT : 1][16], vr[DO_R ? kKrBatch : 1][4];
+            if (DO_L && with_left) {
+                const int m = aL ? j : 0;
+                const FastDiv f = kg.fd[m];
+                const auto rs = fac_rsrc(m);
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    const uint32_t qd = fast_div(idxL[e], f);
+                    const uint32_t i = idxL[e] - qd * f.d;
+                    idxL[e] = qd;
+#pragma unroll
+                    for (int rt = 0; rt < NRT; ++rt) {
+                        const int r = rt * 16 + c16;
+                        const uint32_t off = (aL && r < R) ? (i * (uint32_t)R + (uint32_t)r) * 4 : kOOB;
+                        vl[rt][e] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0));
+                    }
+                }
+            }
+            if (DO_R) {
+                const int m = kg.nstar + (aR ? j : 0);
+                const FastDiv f = kg.fd[m];
+                const auto rs = fac_rsrc(m);
+#pragma unroll
+                for (int u = 0; u < kKrBatch; ++u) {
+                    const uint32_t qd = fast_div(idxR[u], f);
+                    const uint32_t i = idxR[u] - qd * f.d;
+                    idxR[u] = qd;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const int r = r4[u] + c;
+                        const uint32_t off = (aR && r < R) ? (i * (uint32_t)R + (uint32_t)r) * 4 : kOOB;
+                        vr[u][c] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0));
+                    }
+                }
+            }
+            if (DO_L && with_left) {
+#pragma unroll
+                for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) fl[rt][e] *= aL ? vl[rt][e] : 1.f;
+            }
+            if (DO_R) {
+#pragma unroll
+                for (int u = 0; u < kKrBatch; ++u)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) t[u][c] *= aR ? vr[u][c] : 1.f;
+            }
+        }
+        if (DO_L && with_left) {
+#pragma unroll
+            for (int jc = 0; jc < 2; ++jc)
+#pragma unroll
+                for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+                    for (int tt = 0; tt < 8; ++tt) {
+                        const float v = fl[rt][8 * jc + tt];
+                        const unsigned short h = bf16_rne(v);
+                        krl_hi[jc][rt][tt] = h;
+                        if (KLO) krl_lo[DO_L && KLO ? jc : 0][DO_L && KLO ? rt : 0][tt] = bf16_rne(v - bf16_to_f(h));
+                    }
+        }
+        if (DO_R) {
+#pragma unroll
+            for (int u = 0; u < kKrBatch; ++u) {
+                const int e = base + u * 256 + tid;
+                if (e < n4) {
+                    const int kk = e / (RT / 4);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const unsigned short h = bf16_rne(t[u][c]);
+                        sKRh[(r4[u] + c) * KRS + kk] = h;
+                        if (KLO) sKRl[(r4[u] + c) * KRS + kk] = bf16_rne(t[u][c] - bf16_to_f(h));
+                    }
+                }
             }
         }
     };
@@ -149,18 +267,50 @@ __global__ __launch_bounds__(256) void k_contract_bf16(const void* __restrict__ 
 #pragma unroll
         for (int rt = 0; rt < (DO_R ? NRT : 1); ++rt) accR[e][rt] = v4f{0.f, 0.f, 0.f, 0.f};
 
-    if (DO_R) build_krr(0, k_begin);
-    v8us cur_hi[4], cur_lo[4], nxt_hi[4], nxt_lo[4];
-    load_step(cur_hi, cur_lo, k_begin);
-    __syncthreads();
-
-    for (int64_t st = 0; st < nsteps; ++st) {
-        const int64_t k0 = k_begin + st * kB16Step;
+    auto step = [&](Raw& curRaw, Raw& nxtRaw, int64_t st) {
         const int buf = (int)(st & 1);
-        if (st + 1 < nsteps) load_step(nxt_hi, nxt_lo, k0 + kB16Step);
-
+        load_step(nxtRaw, st + kB16Depth);
+        __builtin_amdgcn_sched_barrier(0);   // keep the prefetch ahead of the step's MFMAs
+        v8us cur_hi[4], cur_lo[4];
+        split(curRaw, cur_hi, cur_lo);
+        if (DO_R) {
+            // transpose through this wave's LDS tile: row (32*jc + 8q + t), column (16*kt + c16)
+#pragma unroll
+            for (int part = 0; part < (YLO ? 2 : 1); ++part) {
+                unsigned short* T = sTr[w][YLO ? part : 0];
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const v8us v = part == 0 ? cur_hi[s] : cur_lo[s];
+                    const int col = 16 * (s & 1) + c16;
+                    const int row0 = 32 * (s >> 1) + 8 * q;
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) T[(row0 + t) * kTrLd + col] = v[t];
+                }
+            }
+            lds_wave_sync_b();
+            // right product: rows 16*rr + c16 (output), columns 8q .. 8q+7 (reduced)
+#pragma unroll
+            for (int rt = 0; rt < NRT; ++rt) {
+                const v8us bh = *(const v8us*)(&sKRh[(rt * 16 + c16) * KRS + st * kB16Step + 8 * q]);
+                v8us bl;
+                if (KLO) bl = *(const v8us*)(&sKRl[(rt * 16 + c16) * KRS + st * kB16Step + 8 * q]);
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) {
+                    const v8us ah = *(const v8us*)(&sTr[w][0][(16 * rr + c16) * kTrLd + 8 * q]);
+                    accR[rr][rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(ah), as_bf(bh), accR[rr][rt], 0, 0, 0);
+                    if (KLO)
+                        accR[rr][rt] =
+                            __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(ah), as_bf(bl), accR[rr][rt], 0, 0, 0);
+                    if (YLO) {
+                        const v8us al = *(const v8us*)(&sTr[w][YLO ? 1 : 0][(16 * rr + c16) * kTrLd + 8 * q]);
+                        accR[rr][rt] =
+                            __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(al), as_bf(bh), accR[rr][rt], 0, 0, 0);
+                    }
+                }
+            }
+        }
         if (DO_L) {
-            // left product: columns k0 + 16*kt + c16 are the output rows, rows are reduced
+            // left product: columns step_col(st) + 16*kt + c16 are the output rows, rows are reduced
             v4f accL[2][NRT];
 #pragma unroll
             for (int kt = 0; kt < 2; ++kt)
@@ -183,68 +333,48 @@ __global__ __launch_bounds__(256) void k_contract_bf16(const void* __restrict__ 
             for (int kt = 0; kt < 2; ++kt)
 #pragma unroll
                 for (int rt = 0; rt < NRT; ++rt) sRed[buf][((w * 2 + kt) * NRT + rt) * 64 + l] = accL[kt][rt];
-        }
-        if (DO_R) {
-            // transpose through this wave's LDS tile: row (32*jc + 8q + t), column (16*kt + c16)
+            lds_block_sync_b();
+            // P_L partial stores of this block row over the step's columns (past K: dropped);
+            // every thread stores 2*NRT values (uniform count, exact load counters)
+            const int64_t k0 = step_col(st);
+            const auto lrs = buf_rsrc(PLpart + ((int64_t)blockIdx.x * K + k0) * ld,
+                                      (uint32_t)(max((int64_t)0, min((int64_t)kB16Step, K - k0)) * ld * 4));
 #pragma unroll
-            for (int part = 0; part < (YLO ? 2 : 1); ++part) {
-                unsigned short* T = sTr[w][YLO ? part : 0];
+            for (int jj = 0; jj < NRT; ++jj) {
+                const int item = jj * 128 + (tid >> 1);   // (kt, rt, lane) of the wave partials
+                const int lane = item & 63;
+                const int rt = (item >> 6) % NRT;
+                const int kt = (item >> 6) / NRT;
+                const int v0 = 2 * (tid & 1);
+                const float* src = (const float*)sRed[buf];
+                float s0 = 0.f, s1 = 0.f;
 #pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    const v8us v = part == 0 ? cur_hi[s] : cur_lo[s];
-                    const int col = 16 * (s & 1) + c16;
-                    const int row0 = 32 * (s >> 1) + 8 * q;
-#pragma unroll
-                    for (int t = 0; t < 8; ++t) T[(row0 + t) * kTrLd + col] = v[t];
+                for (int ww = 0; ww < 4; ++ww) {
+                    const float* e = src + (((ww * 2 + kt) * NRT + rt) * 64 + lane) * 4 + v0;
+                    s0 += e[0];
+                    s1 += e[1];
                 }
-            }
-            lds_wave_sync_b();
-            // right product: rows 16*rr + c16 (output), columns 8q .. 8q+7 (reduced)
-#pragma unroll
-            for (int rt = 0; rt < NRT; ++rt) {
-                const v8us bh = *(const v8us*)(&sKR[buf][0][(rt * 16 + c16) * kKrLd + 8 * q]);
-                v8us bl;
-                if (KLO) bl = *(const v8us*)(&sKR[buf][KLO ? 1 : 0][(rt * 16 + c16) * kKrLd + 8 * q]);
-#pragma unroll
-                for (int rr = 0; rr < 4; ++rr) {
-                    const v8us ah = *(const v8us*)(&sTr[w][0][(16 * rr + c16) * kTrLd + 8 * q]);
-                    accR[rr][rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(ah), as_bf(bh), accR[rr][rt], 0, 0, 0);
-                    if (KLO)
-                        accR[rr][rt] =
-                            __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(ah), as_bf(bl), accR[rr][rt], 0, 0, 0);
-                    if (YLO) {
-                        const v8us al = *(const v8us*)(&sTr[w][YLO ? 1 : 0][(16 * rr + c16) * kTrLd + 8 * q]);
-                        accR[rr][rt] =
-                            __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(al), as_bf(bh), accR[rr][rt], 0, 0, 0);
-                    }
-                }
-            }
-        }
-        if (DO_R && st + 1 < nsteps) build_krr(buf ^ 1, k0 + kB16Step);
-        __syncthreads();
-        if (DO_L) {
-            for (int e = tid; e < 2 * NRT * 64; e += 256) {
-                const int lane = e & 63;
-                const int rt = (e >> 6) % NRT;
-                const int kt = (e >> 6) / NRT;
-                v4f s = sRed[buf][((0 * 2 + kt) * NRT + rt) * 64 + lane];
-#pragma unroll
-                for (int ww = 1; ww < 4; ++ww) s += sRed[buf][((ww * 2 + kt) * NRT + rt) * 64 + lane];
                 const int r = rt * 16 + (lane & 15);
-                if (r < ld) {
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int64_t k = k0 + kt * 16 + 4 * (lane >> 4) + v;
-                        if (k < k_end) PLpart[((int64_t)blockIdx.x * K + k) * ld + r] = s[v];
-                    }
-                }
+                const uint32_t off = r < ld ? (uint32_t)(((kt * 16 + 4 * (lane >> 4) + v0) * ld + r) * 4) : kOOB;
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(s0), lrs, (int)off, 0, 0);
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(s1), lrs, (int)(off + (uint32_t)(ld * 4)), 0, 0);
             }
         }
+    };
+
+    // Prologue: the first steps of Y go out first, then the Khatri-Rao rows.
+    constexpr int NB = kB16Depth + 1;
+    Raw rbuf[NB];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            cur_hi[s] = nxt_hi[s];
-            if (YLO) cur_lo[s] = nxt_lo[s];
-        }
+    for (int d = 0; d < kB16Depth; ++d) load_step(rbuf[d], d);
+    gen_kr(0, true);
+    for (int base = kKrBatch * 256; DO_R && base < n4; base += kKrBatch * 256) gen_kr(base, false);   // wide chunks
+    lds_block_sync_b();
+
+    for (int64_t st = 0; st < nsteps; st += NB) {
+#pragma unroll
+        for (int ph = 0; ph < NB; ++ph)
+            if (ph == 0 || st + ph < nsteps) step(rbuf[ph], rbuf[(ph + kB16Depth) % NB], st + ph);
     }
 
     if (DO_R) {
@@ -265,47 +395,71 @@ __global__ __launch_bounds__(256) void k_contract_bf16(const void* __restrict__ 
     }
 }
 
-template <bool TYF, int NRT, bool REFINE>
-static hipError_t launch_b16_roles(const void* Y, int64_t J, int64_t K, const FacSet<float>& fs, int nstar,
-                                   const Tiling& t, int roles, const MfmaBufs& o, hipStream_t s) {
-    dim3 grid((unsigned)t.n_jr, (unsigned)t.n_kc);
-    const int64_t kcols = t.ktb * kB16Step;
-    if (roles == 3)
-        hipLaunchKernelGGL((k_contract_bf16<TYF, NRT, true, true, REFINE>), grid, dim3(256), 0, s, Y, J, K, fs, nstar,
-                           kcols, o.ld, o.PRpart, o.PLpart);
-    else if (roles == 1)
-        hipLaunchKernelGGL((k_contract_bf16<TYF, NRT, true, false, REFINE>), grid, dim3(256), 0, s, Y, J, K, fs,
-                           nstar, kcols, o.ld, o.PRpart, o.PLpart);
-    else if (roles == 2)
-        hipLaunchKernelGGL((k_contract_bf16<TYF, NRT, false, true, REFINE>), grid, dim3(256), 0, s, Y, J, K, fs,
-                           nstar, kcols, o.ld, o.PRpart, o.PLpart);
-    else
-        return hipErrorInvalidValue;
+// LDS of one block: static transpose / reduction tiles plus the dynamic KR_R tiles.
+static constexpr int64_t b16_static_lds(int nrt, bool do_r, bool do_l, bool ylo) {
+    return (do_r ? (int64_t)4 * (ylo ? 2 : 1) * 64 * kTrLd * 2 : 0) + (do_l ? (int64_t)2 * 4 * 2 * nrt * 64 * 16 : 0);
+}
+constexpr int64_t kB16LdsPerCu = 160 * 1024;
+
+int64_t mfma_bf16_max_cols(int rt, int roles, bool ylo, bool klo) {
+    const int nrt = rt / 16;
+    const int64_t st = b16_static_lds(nrt, (roles & 1) != 0, (roles & 2) != 0, ylo);
+    if (!(roles & 1)) return int64_t(1) << 30;   // no KR_R tile
+    const int64_t per_col = (int64_t)(klo ? 2 : 1) * rt * 2;
+    const int64_t cols = (kB16LdsPerCu - st - (int64_t)(klo ? 2 : 1) * rt * 2 * 8) / per_col;
+    return std::max<int64_t>(kB16Step, cols / kB16Step * kB16Step);
+}
+
+template <bool TYF, int NRT, bool DO_R, bool DO_L, bool REFINE>
+static hipError_t launch_b16_one(dim3 grid, const void* Y, int64_t J, int64_t K, int64_t kcols, const MfmaBufs& o,
+                                 hipStream_t s) {
+    auto kern = k_contract_bf16<TYF, NRT, DO_R, DO_L, REFINE>;
+    const size_t dyn = DO_R ? (size_t)(REFINE ? 2 : 1) * NRT * 16 * krr_stride(kcols) * 2 : 0;
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)(kB16LdsPerCu - b16_static_lds(NRT, DO_R, DO_L, TYF && REFINE)));
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(kern, grid, dim3(256), dyn, s, Y, J, K, kcols, o.ld, o.kg, o.PRpart, o.PLpart);
     return hipGetLastError();
 }
 
+template <bool TYF, int NRT, bool REFINE>
+static hipError_t launch_b16_roles(const void* Y, int64_t J, int64_t K, const Tiling& t, int roles,
+                                   const MfmaBufs& o, hipStream_t s) {
+    dim3 grid((unsigned)t.n_jr, (unsigned)t.n_kc);
+    const int64_t kcols = t.ktb * kB16Step;
+    if (kcols > mfma_bf16_max_cols(NRT * 16, roles, TYF && REFINE, REFINE)) return hipErrorInvalidValue;
+    if (roles == 3) return launch_b16_one<TYF, NRT, true, true, REFINE>(grid, Y, J, K, kcols, o, s);
+    if (roles == 1) return launch_b16_one<TYF, NRT, true, false, REFINE>(grid, Y, J, K, kcols, o, s);
+    if (roles == 2) return launch_b16_one<TYF, NRT, false, true, REFINE>(grid, Y, J, K, kcols, o, s);
+    return hipErrorInvalidValue;
+}
+
 template <bool TYF, bool REFINE>
-static hipError_t launch_b16_nrt(const void* Y, int64_t J, int64_t K, const FacSet<float>& fs, int nstar,
-                                 const Tiling& t, int roles, const MfmaBufs& o, hipStream_t s) {
+static hipError_t launch_b16_nrt(const void* Y, int64_t J, int64_t K, const Tiling& t, int roles, const MfmaBufs& o,
+                                 hipStream_t s) {
     switch (t.rt) {
-        case 16: return launch_b16_roles<TYF, 1, REFINE>(Y, J, K, fs, nstar, t, roles, o, s);
-        case 32: return launch_b16_roles<TYF, 2, REFINE>(Y, J, K, fs, nstar, t, roles, o, s);
-        case 48: return launch_b16_roles<TYF, 3, REFINE>(Y, J, K, fs, nstar, t, roles, o, s);
-        case 64: return launch_b16_roles<TYF, 4, REFINE>(Y, J, K, fs, nstar, t, roles, o, s);
+        case 16: return launch_b16_roles<TYF, 1, REFINE>(Y, J, K, t, roles, o, s);
+        case 32: return launch_b16_roles<TYF, 2, REFINE>(Y, J, K, t, roles, o, s);
+        case 48: return launch_b16_roles<TYF, 3, REFINE>(Y, J, K, t, roles, o, s);
+        case 64: return launch_b16_roles<TYF, 4, REFINE>(Y, J, K, t, roles, o, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_contract_bf16(int ydt, int mode, const void* Y, int64_t J, int64_t K, const FacSet<float>& fs,
-                                int nstar, const Tiling& t, int roles, const MfmaBufs& o, hipStream_t stream) {
+hipError_t launch_contract_bf16(int ydt, int mode, const void* Y, int64_t J, int64_t K, const Tiling& t, int roles,
+                                const MfmaBufs& o, hipStream_t stream) {
     if ((J % 8) != 0) return hipErrorInvalidValue;
     const bool refine = mode == CPG_MODE_BF16_REFINED;
     if (ydt == CPG_F32)
-        return refine ? launch_b16_nrt<true, true>(Y, J, K, fs, nstar, t, roles, o, stream)
-                      : launch_b16_nrt<true, false>(Y, J, K, fs, nstar, t, roles, o, stream);
+        return refine ? launch_b16_nrt<true, true>(Y, J, K, t, roles, o, stream)
+                      : launch_b16_nrt<true, false>(Y, J, K, t, roles, o, stream);
     if (ydt == CPG_BF16)
-        return refine ? launch_b16_nrt<false, true>(Y, J, K, fs, nstar, t, roles, o, stream)
-                      : launch_b16_nrt<false, false>(Y, J, K, fs, nstar, t, roles, o, stream);
+        return refine ? launch_b16_nrt<false, true>(Y, J, K, t, roles, o, stream)
+                      : launch_b16_nrt<false, false>(Y, J, K, t, roles, o, stream);
     return hipErrorInvalidValue;
 }
 
