@@ -19,6 +19,9 @@
 #ifndef CPG_EPI_MARK
 #define CPG_EPI_MARK(k)
 #endif
+#ifndef CPG_EPI_WMARK
+#define CPG_EPI_WMARK(k)
+#endif
 
 namespace cpg {
 
@@ -445,58 +448,76 @@ __device__ __forceinline__ void block_gamma(const EpiArgs<TC>& a, int n, double*
 }
 
 // One wave: W = L^{-1} for Gamma = L L^T (Gamma in sGam, stride RT), written
-// to sW (stride RT, zero above the diagonal).  Lane i keeps row i in
-// registers; entries of other rows arrive by lane broadcasts, so the whole
-// factorisation runs without block barriers.  Rows and columns R..RT-1 are
+// to sW (stride RT, zero above the diagonal); rows and columns R..RT-1 are
 // padded with the identity.  Cholesky in the row (dot-product) form
 //   L_jj = sqrt(Gamma_jj - sum_{k<j} L_jk^2),
-//   L_ij = (Gamma_ij - sum_{k<j} L_ik L_jk) / L_jj          (i > j),
-// then W row by row from W L = I, column j from RT-1 down to 0:
-//   W_ij = (delta_ij - sum_{k>j} W_ik L_kj) / L_jj,
-// overwriting L_ij once column j of L has been broadcast.  Returns false on a
-// pivot that is not positive and finite (uniform over the wave).
+//   L_ij = (Gamma_ij - sum_{k<j} L_ik L_jk) / L_jj          (i > j):
+// lane i keeps row i in registers and publishes each new entry L_ij to LDS
+// (sLs, stride RT; 1/L_jj after the RT x RT entries); at column j every lane
+// reads row j back as a broadcast and forms the pivot itself, so no lane
+// waits on another beyond the wave's in-order LDS traffic.  Then W column by
+// column, lane c independently:
+//   W_cc = 1/L_cc,  W_ic = -(sum_{c<=k<i} L_ik W_kc) / L_ii   (i > c),
+// with the rows of L read from LDS.  Returns false on a pivot that is not
+// positive and finite (uniform over the wave).
 template <int RT>
-__device__ __forceinline__ bool wave_chol_inverse(const double* sGam, int R, double jit, double* sW) {
-    const int l = threadIdx.x & 63;
-    double x[RT];
+__device__ __forceinline__ bool wave_chol_inverse(const double* sGam, int R, double jit, double* sLs, double* sW) {
+    // lane id read here (not hoistable): the lane masks of the unrolled
+    // columns then live only inside this function instead of the whole kernel
+    int l;
+    asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(l));
+    double* sDinv = sLs + RT * RT;
+    auto gam = [&](int i, int k) -> double {
+        return (i < R && k < R) ? sGam[i * RT + k] + (i == k ? jit : 0.0) : (i == k ? 1.0 : 0.0);
+    };
+    double x[RT], diag[RT];
 #pragma unroll
-    for (int k = 0; k < RT; ++k)
-        x[k] = (l < R && k < R) ? sGam[l * RT + k] + (l == k ? jit : 0.0) : (l == k ? 1.0 : 0.0);
+    for (int k = 0; k < RT; ++k) {
+        x[k] = l < RT ? gam(l, k) : 0.0;
+        diag[k] = gam(k, k);
+    }
     bool bad = false;
-    double dv = 1.0;   // lane j: 1 / L_jj
+    CPG_EPI_WMARK(0);
 #pragma unroll
     for (int j = 0; j < RT; ++j) {
-        // the dot products over k < j in four interleaved partial sums (short dependency chains)
+        double Lj[j > 0 ? j : 1];
+#pragma unroll
+        for (int k = 0; k < j; ++k) Lj[k] = sLs[j * RT + k];
+        const double gjj = diag[j];
         double sv[4] = {0.0, 0.0, 0.0, 0.0}, st[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int k = 0; k < j; ++k) {
-            const double Ljk = readlane_d(x[k], j);
-            sv[k & 3] += Ljk * Ljk;
-            st[k & 3] += x[k] * Ljk;
+            sv[k & 3] += Lj[k] * Lj[k];
+            st[k & 3] += x[k] * Lj[k];
         }
-        const double v = readlane_d(x[j], j) - ((sv[0] + sv[1]) + (sv[2] + sv[3]));
+        const double v = gjj - ((sv[0] + sv[1]) + (sv[2] + sv[3]));
         const double t = x[j] - ((st[0] + st[1]) + (st[2] + st[3]));
         bad = bad || !(v > 0.0) || !isfinite(v);
         const double y = rsqrt_d(v);
         x[j] = l > j ? t * y : (l == j ? v * y : x[j]);
-        dv = l == j ? y : dv;
-        __builtin_amdgcn_sched_barrier(0);  // keep each step's broadcasts short-lived
-    }
-    if (bad) return false;
-#pragma unroll
-    for (int j = RT - 1; j >= 0; --j) {
-        const double dj = readlane_d(dv, j);
-        double st[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int k = j + 1; k < RT; ++k) st[k & 3] += x[k] * readlane_d(x[j], k);
-        const double t = (l == j ? 1.0 : 0.0) - ((st[0] + st[1]) + (st[2] + st[3]));
-        x[j] = l >= j ? t * dj : 0.0;
+        if (l >= j && l < RT) sLs[l * RT + j] = x[j];
+        if (l == j) sDinv[j] = y;
+        wave_lds_sync();
         __builtin_amdgcn_sched_barrier(0);
     }
+    CPG_EPI_WMARK(1);
+    if (bad) return false;
+    double wv[RT];
+#pragma unroll
+    for (int i = 0; i < RT; ++i) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < i; ++k) acc[k & 3] += sLs[i * RT + k] * wv[k];
+        const double di = sDinv[i];
+        wv[i] = l == i ? di : (l < i ? -((acc[0] + acc[1]) + (acc[2] + acc[3])) * di : 0.0);
+        __builtin_amdgcn_sched_barrier(0);   // one row of L in registers at a time
+    }
+    CPG_EPI_WMARK(2);
     if (l < RT) {
 #pragma unroll
-        for (int k = 0; k < RT; ++k) sW[l * RT + k] = x[k];
+        for (int i = 0; i < RT; ++i) sW[i * RT + l] = wv[i];
     }
+    CPG_EPI_WMARK(3);
     return true;
 }
 
@@ -513,6 +534,7 @@ __device__ __forceinline__ bool block_solve(const EpiArgs<TC>& a, int n, const d
         return block_solve_lds<TC, RT>(a, n, sG, sGam, sL, sA, spart, sOk);
     } else {
         static_assert(2 * RT * RT <= kEpiThreads, "two threads per Gram entry");
+        static_assert(RT * RT + RT <= kEpiThreads, "Cholesky scratch fits the partial-sum buffer");
         const int tid = threadIdx.x;
         const int R = a.fs.R;
         const int64_t I = a.fs.dims[n];
@@ -520,10 +542,12 @@ __device__ __forceinline__ bool block_solve(const EpiArgs<TC>& a, int n, const d
         __syncthreads();
         CPG_EPI_MARK(20);
         if (tid < 64) {
-            double tr = 0.0;
-            for (int c = 0; c < R; ++c) tr += sGam[c * RT + c];
-            bool good = wave_chol_inverse<RT>(sGam, R, 0.0, sL);
-            if (!good) good = wave_chol_inverse<RT>(sGam, R, 1e-12 * tr / R, sL);
+            bool good = wave_chol_inverse<RT>(sGam, R, 0.0, spart, sL);
+            if (!good) {
+                double tr = 0.0;
+                for (int c = 0; c < R; ++c) tr += sGam[c * RT + c];
+                good = wave_chol_inverse<RT>(sGam, R, 1e-12 * tr / R, spart, sL);
+            }
             if (tid == 0) *sOk = good ? 1 : 0;
         }
         __syncthreads();
