@@ -18,6 +18,7 @@ __all__ = [
     "mttkrp", "cp_gradient_all", "gradient_entry", "n_star", "gram", "gamma",
     "cholesky_jitter_solve", "NotSPD", "als_order", "als_sweep", "cp_als", "cp_full",
     "cost_explicit", "cost_identity", "fit_from_cost", "norm2", "e_gradient_all",
+    "gradient_row",
 ]
 
 JITTER = 1e-12
@@ -112,11 +113,25 @@ def gradient_entry(Y, A, n, i, r):
     a_r^(k) along every other mode k (Def. 2.3 mode products), float64.
     Used to check single entries of the gradient on tensors too big for the
     full unfoldings."""
-    S = np.take(Y, i, axis=n)          # (N-1)-way slice
+    S = Y[(slice(None),) * n + (i,)]   # (N-1)-way slice (a view: no copy of Y)
     modes = [k for k in range(Y.ndim) if k != n]
     for ax in reversed(range(S.ndim)):  # contract the last axis each time
         S = np.tensordot(S, A[modes[ax]][:, r], axes=([ax], [0]))
     return float(S)
+
+
+def gradient_row(Y, A, n, i):
+    """Row i of G^(n) (eq. 3.2 for every r at once): the slice Y(i_n = i)
+    contracted along every other mode k with A^(k), keeping the rank index,
+    float64.  For sampling rows of the gradient of large tensors."""
+    S = np.ascontiguousarray(Y[(slice(None),) * n + (i,)])   # (N-1)-way slice, copied alone
+    modes = [k for k in range(Y.ndim) if k != n]
+    # contract the last slice axis with A^(last), then each remaining axis
+    # against the matching factor while keeping r (a Hadamard step over r)
+    T = np.tensordot(S, A[modes[-1]], axes=([S.ndim - 1], [0]))   # (..., R)
+    for ax in reversed(range(S.ndim - 1)):
+        T = np.einsum("...jr,jr->...r", T, A[modes[ax]])
+    return np.asarray(T, dtype=np.float64)
 
 
 def e_gradient_all(Y, A):

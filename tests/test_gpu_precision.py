@@ -75,21 +75,21 @@ def test_bf16_refined_is_more_accurate_than_plain_bf16():
 
 
 def test_full_size_7d_bf16_refined_sampled():
-    """10^7 tensor, rank 10, float32 storage: sampled entries of every mode's
-    gradient against the oracle's element-wise definition (eq. 3.2)."""
+    """10^7 tensor, rank 10, float32 storage: sampled rows of every mode's
+    gradient against the oracle's definition (eq. 3.2), entry by entry."""
     w = cpgen.WORKLOADS["cp7d_10_r10_f32"]
     pr = cpgen.make_problem(w, rep=0)
     A, G = _run(pr, "f32", "bf16_refined")
     Y = exact_tensor(pr["y"], "f32", pr["dims"])
     Ax = exact_factors(A)
     Aabs = [np.abs(M) for M in Ax]
+    Yabs = np.abs(Y)
     g = np.random.default_rng(5)
     for n in range(7):
-        for _ in range(3):
-            i, r = int(g.integers(10)), int(g.integers(10))
-            ref = O.gradient_entry(Y, Ax, n, i, r)
-            gab = O.gradient_entry(np.abs(Y), Aabs, n, i, r)
-            assert abs(G[n][i, r] - ref) <= BOUND["bf16_refined"] * gab, (n, i, r)
+        for i in g.choice(10, size=2, replace=False):
+            ref = O.gradient_row(Y, Ax, n, int(i))
+            gab = O.gradient_row(Yabs, Aabs, n, int(i))
+            assert np.all(np.abs(G[n][i] - ref) <= BOUND["bf16_refined"] * gab), (n, i)
 
 
 def test_als_sweep_in_bf16_refined_mode():
@@ -109,3 +109,41 @@ def test_als_sweep_in_bf16_refined_mode():
     for n in range(len(dims)):
         assert rel_fro(exact_factors(A)[n], A_ref[n]) < 1e-3
     assert abs(fit - fit_ref) < 1e-4
+
+
+def test_full_size_5d_bf16_stored_sampled_and_als():
+    """48^5 tensor stored as bf16 (255M entries), rank 32, congruent factors,
+    in the launch configuration the library picks for it: sampled rows of
+    every mode's gradient against the definition (eq. 3.2), entry by entry within
+    the refined rounding bound, then one ALS sweep, whose cost may not exceed
+    the cost of the starting factors (eq. 2.14 minimises it mode by mode)."""
+    import paper_1204_1586_amd as P
+    w = cpgen.WORKLOADS["cp5d_48_r32_bf16"]
+    print(f"[bf16 full] dims={w.dims} R={w.rank}", flush=True)
+    pr = cpgen.make_problem(w, rep=0)
+    dims, R = pr["dims"], pr["R"]
+    Yd = to_device_y(pr["y"], "bf16")
+    A = to_device_factors(pr["init"], "f32")
+    G = [torch.empty_like(M) for M in A]
+    plan = P.cpgrad_plan(dims, R, "bf16", "f32", "bf16_refined")
+    P.cpgrad_all_modes(plan, Yd, A, G)
+    torch.cuda.synchronize()
+    Gh = [g.cpu().double().numpy() for g in G]
+    Y = exact_tensor(pr["y"], "bf16", dims)
+    Ax = exact_factors(A)
+    Aabs = [np.abs(M) for M in Ax]
+    Yabs = np.abs(Y)
+    g = np.random.default_rng(7)
+    for n in range(5):
+        for i in g.choice(dims[n], size=2, replace=False):
+            ref = O.gradient_row(Y, Ax, n, int(i))
+            gab = O.gradient_row(Yabs, Aabs, n, int(i))
+            assert np.all(np.abs(Gh[n][i] - ref) <= BOUND["bf16_refined"] * gab), (n, i)
+        print(f"  mode {n + 1}: rows checked", flush=True)
+    del Y, Yabs
+    P.cpgrad_bind(plan, Yd)
+    c0, f0 = P.cp_fit(plan, Yd, A)
+    c1, f1 = P.cpals_step(plan, Yd, A)
+    print(f"  cost {c0:.6e} -> {c1:.6e}, fit {f0:.6f} -> {f1:.6f}", flush=True)
+    assert np.isfinite(c1) and 0.0 <= f1 <= 1.0
+    assert c1 <= c0 * (1 + 1e-5)

@@ -166,6 +166,27 @@ def test_gradient_entry_matches_full():
                 assert abs(O.gradient_entry(Y, A, n, i, r) - G[i, r]) < 1e-12
 
 
+def test_gradient_row_matches_entries_and_full():
+    """Rows of G^(n) from the slice contraction agree with the element-wise
+    sums (eq. 3.2) and with Algorithm 1; a transposed factor (a planted
+    mistake in the oracle's contraction order) would not."""
+    dims = (4, 3, 5, 2, 3)
+    g = np.random.default_rng(11)
+    Y = O.as_tensor(g.standard_normal(int(np.prod(dims))), dims)
+    A = _rand_factors(dims, 3, 12)
+    for n in range(5):
+        G = O.mttkrp(Y, A, n)
+        for i in range(dims[n]):
+            row = O.gradient_row(Y, A, n, i)
+            assert np.allclose(row, G[i], rtol=1e-13, atol=1e-13)
+            assert abs(row[1] - O.gradient_entry(Y, A, n, i, 1)) < 1e-12
+    # planted: the factors of modes 2 and 5 (both of size 3) swapped
+    n, i = 3, 1
+    S = np.take(Y, i, axis=n)   # axes: modes 1, 2, 3, 5
+    bad = np.einsum("abcd,ar,br,cr,dr->r", S, A[0], A[4], A[2], A[1])
+    assert not np.allclose(bad, O.gradient_row(Y, A, n, i), rtol=1e-6)
+
+
 # --------------------------------------------------------------------------
 # n* (Algorithm 2, step 1)
 # --------------------------------------------------------------------------
