@@ -91,6 +91,8 @@ struct MfmaBufs {
     float* PLpart;
     int ld;             // row stride (padded rank) of the partials
     KrGen kg;           // factors for the Khatri-Rao rows
+    hipEvent_t ev0;     // if set: recorded at the kernel's start and end (launch-attached timing)
+    hipEvent_t ev1;
 };
 hipError_t launch_contract_mfma(int ydt, int mode, const void* Y, int64_t J, int64_t K, const Tiling& t,
                                 int roles, const MfmaBufs& bufs, hipStream_t stream);

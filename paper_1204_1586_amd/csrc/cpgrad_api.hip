@@ -254,10 +254,10 @@ static KrGen kr_gen(const cpgrad_plan_s* p, const FacSet<float>& fs) {
 }
 
 static hipError_t launch_contract(cpgrad_plan_s* p, const void* Y, const AnyFacSet& fs, const Tiling& t,
-                                  int roles) {
+                                  int roles, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
     if (t.n_kc > 65535) return hipErrorInvalidConfiguration;
     if (t.kernel == 2 || t.kernel == 3) {
-        MfmaBufs o{(float*)p->PRpart, (float*)p->PLpart, p->ld, kr_gen(p, fs.f)};
+        MfmaBufs o{(float*)p->PRpart, (float*)p->PLpart, p->ld, kr_gen(p, fs.f), ev0, ev1};
         if (t.kernel == 3)
             return launch_contract_bf16(p->ydt, p->mode, Y, p->J, p->K, t, roles, o, p->stream);
         return launch_contract_mfma(p->ydt, p->mode, Y, p->J, p->K, t, roles, o, p->stream);
@@ -266,8 +266,9 @@ static hipError_t launch_contract(cpgrad_plan_s* p, const void* Y, const AnyFacS
                                 p->PRpart, p->PLpart, p->stream);
 }
 
-// Launch one big contraction; with profiling on, bracket it with HIP events
-// recorded on the plan's stream.
+// Launch one big contraction; with profiling on, time it with HIP events on
+// the plan's stream (attached to the launch for the matrix-core kernels, so
+// they bracket exactly the kernel's execution; recorded around it otherwise).
 static hipError_t run_contract(cpgrad_plan_s* p, const void* Y, const AnyFacSet& fs, const Tiling& t, int roles) {
     if (!p->profile) return launch_contract(p, Y, fs, t, roles);
     if (p->ev_used == p->ev_start.size()) {
@@ -283,6 +284,8 @@ static hipError_t run_contract(cpgrad_plan_s* p, const void* Y, const AnyFacSet&
     }
     const size_t i = p->ev_used++;
     p->ev_roles[i] = roles;
+    if (t.kernel == 2 || t.kernel == 3)   // events attached to the kernel launch itself
+        return launch_contract(p, Y, fs, t, roles, p->ev_start[i], p->ev_stop[i]);
     hipError_t e = hipEventRecord(p->ev_start[i], p->stream);
     if (e != hipSuccess) return e;
     e = launch_contract(p, Y, fs, t, roles);

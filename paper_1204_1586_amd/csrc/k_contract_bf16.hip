@@ -28,6 +28,8 @@
 
 #include <algorithm>
 
+#include <hip/hip_ext.h>
+
 namespace cpg {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -422,7 +424,11 @@ static hipError_t launch_b16_one(dim3 grid, const void* Y, int64_t J, int64_t K,
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL(kern, grid, dim3(256), dyn, s, Y, J, K, kcols, o.ld, o.kg, o.PRpart, o.PLpart);
+    if (o.ev0)
+        hipExtLaunchKernelGGL(kern, grid, dim3(256), (uint32_t)dyn, s, o.ev0, o.ev1, 0u, Y, J, K, kcols, o.ld, o.kg,
+                              o.PRpart, o.PLpart);
+    else
+        hipLaunchKernelGGL(kern, grid, dim3(256), dyn, s, Y, J, K, kcols, o.ld, o.kg, o.PRpart, o.PLpart);
     return hipGetLastError();
 }
 

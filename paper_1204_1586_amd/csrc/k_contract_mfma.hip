@@ -24,6 +24,8 @@
 
 #include <algorithm>
 
+#include <hip/hip_ext.h>
+
 namespace cpg {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -390,7 +392,11 @@ static hipError_t launch_one(dim3 grid, const float* Y, int64_t J, int64_t K, in
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL(kern, grid, dim3(256), dyn, s, Y, J, K, kcols, o.ld, o.kg, o.PRpart, o.PLpart);
+    if (o.ev0)
+        hipExtLaunchKernelGGL(kern, grid, dim3(256), (uint32_t)dyn, s, o.ev0, o.ev1, 0u, Y, J, K, kcols, o.ld, o.kg,
+                              o.PRpart, o.PLpart);
+    else
+        hipLaunchKernelGGL(kern, grid, dim3(256), dyn, s, Y, J, K, kcols, o.ld, o.kg, o.PRpart, o.PLpart);
     return hipGetLastError();
 }
 
