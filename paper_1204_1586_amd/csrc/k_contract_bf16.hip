@@ -128,6 +128,7 @@ __global__ __launch_bounds__(256) void k_contract_bf16(const void* __restrict__ 
             }
         }
     };
+    // hi / lo split with the hardware conversion (round to nearest even)
     auto split = [&](const Raw& r, v8us (&hi)[4], v8us (&lo)[4]) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -136,9 +137,9 @@ __global__ __launch_bounds__(256) void k_contract_bf16(const void* __restrict__ 
                                     r.b[s][0], r.b[s][1], r.b[s][2], r.b[s][3]};
 #pragma unroll
                 for (int t = 0; t < 8; ++t) {
-                    const unsigned short h = bf16_rne(x[t]);
-                    hi[s][t] = h;
-                    if (YLO) lo[s][t] = bf16_rne(x[t] - bf16_to_f(h));
+                    const __bf16 h = (__bf16)x[t];
+                    hi[s][t] = __builtin_bit_cast(unsigned short, h);
+                    if (YLO) lo[s][t] = __builtin_bit_cast(unsigned short, (__bf16)(x[t] - (float)h));
                 }
             } else {
                 hi[s] = r.c[s];
@@ -277,16 +278,33 @@ __global__ __launch_bounds__(256) void k_contract_bf16(const void* __restrict__ 
         split(curRaw, cur_hi, cur_lo);
         if (DO_R) {
             // transpose through this wave's LDS tile: row (32*jc + 8q + t), column (16*kt + c16)
+            // Lanes of adjacent columns (c16 even / odd) swap half of their eight
+            // rows (one DPP exchange of two 32-bit words), so each lane writes four
+            // 32-bit words holding both columns of a row: the even lane rows 0..3,
+            // the odd lane rows 4..7.
+            const bool odd = (c16 & 1) != 0;
 #pragma unroll
             for (int part = 0; part < (YLO ? 2 : 1); ++part) {
-                unsigned short* T = sTr[w][YLO ? part : 0];
+                unsigned int* T = (unsigned int*)sTr[w][YLO ? part : 0];
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
                     const v8us v = part == 0 ? cur_hi[s] : cur_lo[s];
-                    const int col = 16 * (s & 1) + c16;
-                    const int row0 = 32 * (s >> 1) + 8 * q;
+                    typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+                    const v4u own = __builtin_bit_cast(v4u, v);   // word k = rows 2k (low) and 2k+1 (high)
+                    const unsigned int snd0 = odd ? own[0] : own[2], snd1 = odd ? own[1] : own[3];
+                    const unsigned int rcv0 = (unsigned int)__builtin_amdgcn_mov_dpp((int)snd0, 0xB1, 0xF, 0xF, true);
+                    const unsigned int rcv1 = (unsigned int)__builtin_amdgcn_mov_dpp((int)snd1, 0xB1, 0xF, 0xF, true);
+                    // this lane's four rows of its own column and of the neighbour's
+                    const unsigned int mw0 = odd ? own[2] : own[0], mw1 = odd ? own[3] : own[1];
+                    const unsigned int mine[4] = {mw0 & 0xffffu, mw0 >> 16, mw1 & 0xffffu, mw1 >> 16};
+                    const unsigned int nb[4] = {rcv0 & 0xffffu, rcv0 >> 16, rcv1 & 0xffffu, rcv1 >> 16};
+                    const int col2 = (16 * (s & 1) + (c16 & ~1)) >> 1;   // 32-bit column of the pair
+                    const int row0 = 32 * (s >> 1) + 8 * q + (odd ? 4 : 0);
 #pragma unroll
-                    for (int t = 0; t < 8; ++t) T[(row0 + t) * kTrLd + col] = v[t];
+                    for (int k = 0; k < 4; ++k) {
+                        const unsigned int word = odd ? (nb[k] | (mine[k] << 16)) : (mine[k] | (nb[k] << 16));
+                        T[(row0 + k) * (kTrLd / 2) + col2] = word;
+                    }
                 }
             }
             lds_wave_sync_b();
