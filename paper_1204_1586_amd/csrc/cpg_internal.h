@@ -103,35 +103,37 @@ bool mfma_supported(int ydt, int fdt, int mode, int R);
 int64_t mfma_f32_max_cols(int rt, int roles);
 int64_t mfma_bf16_max_cols(int rt, int roles, bool ylo, bool klo);
 
-// One side of the fused partial reduction + first-mode gradient (float32).
+// One side of the fused partial reduction (float32): output row i of a side is
+//   G(i, r) = sum_t Z(row(i, t), r) KR(t, r),  Z = sum_p parts[p]  (float64, p in order)
+// with KR the Khatri-Rao rows of modes kr_first.. (one mode: a single chain
+// step, eqs. 3.20 / 3.22; the side's other modes: its first gradient, eqs.
+// 3.12 / 3.16).
 struct ReduceFirst {
     const float* parts;   // nparts x rows x ld split partials of the side's chain tensor
     int64_t nparts;
     int64_t rows;         // J (right) or K (left)
     int ld;
-    int side;             // 0 = right: rows t + T*i;  1 = left: rows i + I*t
-    int64_t I;            // rows of the gradient (I_n of the side's first mode)
-    int64_t T;            // terms per gradient entry (J_{n-1} right, K_n left)
-    int kr_first;         // the side's remaining modes (0-based), whose Khatri-Rao rows weight the terms
+    int side;             // term t of output row i sits in row T*i + t (0) or i + I*t (1)
+    int64_t I;            // output rows (one block each)
+    int64_t T;            // terms per output row
+    int kr_first;         // modes (0-based) whose Khatri-Rao rows weight the terms
     int kr_count;
-    float* Z;             // rows x ld reduced chain tensor (out)
-    float* G;             // I x R gradient (out)
+    float* Z;             // rows x ld reduced chain tensor (out), or null when nothing reads it
+    float* G;             // I x out_ld result (out)
+    int out_ld;           // R (a gradient) or ld (a chain buffer: columns R..ld-1 written as zero)
 };
+constexpr int kMaxReduceSides = 4;
+// Output rows per block of a side: where the terms of one output row lie
+// I rows apart (side 1), neighbouring output rows share each 128-byte line, so
+// a block takes as many as fill one line.
+inline __host__ __device__ int rf_rows_per_block(int side, int ld) {
+    int r = 1;   // a power of two
+    if (side == 1)
+        while (2 * r * ld * 4 <= 128) r *= 2;
+    return r;
+}
 hipError_t launch_reduce_first(const ReduceFirst* sides, int nsides, const KrGen& kg, double* grams,
                                hipStream_t stream);
-
-// First chain step of one side for the all-mode gradient (float32, many blocks).
-struct TtvFirst {
-    const float* Z;       // rows x ld chain tensor of the side's first mode
-    int ld;
-    int side;             // 0 = right: rows t + T*i;  1 = left: rows i + I*t
-    int64_t I;            // size of the mode contracted away (I_{n*} right, I_{n*+1} left)
-    int64_t T;            // rows of the result (J_{n*-1} right, K_{n*+1} left)
-    const float* A;       // I x R factor of that mode
-    float* out;           // T x out_ld result
-    int out_ld;           // ld (chain buffer) or R (the next mode's gradient itself)
-};
-hipError_t launch_ttv_first(const TtvFirst* sides, int nsides, int R, hipStream_t stream);
 
 // out[row][r] = sum_p parts[p][row][r] over rows x ld entries (float64, fixed order)
 hipError_t launch_reduce_parts(int fdt, const void* parts, int64_t nparts, int64_t rows, int ld,

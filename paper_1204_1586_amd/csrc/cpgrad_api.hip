@@ -301,24 +301,43 @@ static hipError_t run_contract(cpgrad_plan_s* p, const void* Y, const AnyFacSet&
 
 // Reduce the partials of a pass into P_R and/or P_L.  On the fused path a
 // side whose first gradient is wanted (Gr: G^(n*), Gl: G^(n*+1)) gets it from
-// the same kernel, which also computes every Gram when `grams` is set.
+// the same kernel, which also computes every Gram when `grams` is set.  With
+// `Gall` (the all-mode gradient, both sides fused) the kernel also takes the
+// first chain step of each side straight from the partials: its result is
+// the next mode's gradient (Gall) or the chain buffer the epilogue continues
+// from, and P_R / P_L are not stored, since nothing reads them afterwards.
 // Returns CPG_OK; *fused tells whether the gradients were formed.
 static int finish_partials(cpgrad_plan_s* p, const FacSet<float>* fs, const Tiling& t, int roles, void* Gr = nullptr,
-                           void* Gl = nullptr, bool grams = false, bool* fused = nullptr) {
+                           void* Gl = nullptr, bool grams = false, bool* fused = nullptr, void* const* Gall = nullptr) {
     const bool fr = p->fused_first && fs && (roles & 1) && Gr;
     const bool fl = p->fused_first && fs && (roles & 2) && Gl;
     if (fused) *fused = fr || fl;
     if (fr || fl) {
-        ReduceFirst sd[2];
-        int ns = 0;
+        const bool tail = Gall && fr && fl;
+        const int N = p->N, ns = p->nstar, R = p->R, ld = p->ld;
+        ReduceFirst sd[kMaxReduceSides];
+        int n = 0;
         if (fr)
-            sd[ns++] = ReduceFirst{(const float*)p->PRpart, t.n_kc, p->J, p->ld, 0, p->dims[p->nstar - 1],
-                                   p->Jn[p->nstar - 1], 0, p->nstar - 1, (float*)p->PR, (float*)Gr};
+            sd[n++] = ReduceFirst{(const float*)p->PRpart, t.n_kc, p->J, ld, 0, p->dims[ns - 1], p->Jn[ns - 1],
+                                  0, ns - 1, tail ? nullptr : (float*)p->PR, (float*)Gr, R};
         if (fl)
-            sd[ns++] = ReduceFirst{(const float*)p->PLpart, t.n_jr, p->K, p->ld, 1, p->dims[p->nstar],
-                                   p->Kn[p->nstar + 1], p->nstar + 1, p->N - p->nstar - 1, (float*)p->PL,
-                                   (float*)Gl};
-        CPG_TRY(launch_reduce_first(sd, ns, kr_gen(p, *fs), grams ? p->grams : nullptr, p->stream));
+            sd[n++] = ReduceFirst{(const float*)p->PLpart, t.n_jr, p->K, ld, 1, p->dims[ns], p->Kn[ns + 1],
+                                  ns + 1, N - ns - 1, tail ? nullptr : (float*)p->PL, (float*)Gl, R};
+        if (tail && ns >= 2) {
+            // right (eq. 3.20): out(t, r) = sum_i Z(t + T i, r) A^(n*)(i, r), T = J_{n*-1};
+            // G^(1) itself when n* = 2
+            const bool last = ns == 2;
+            sd[n++] = ReduceFirst{(const float*)p->PRpart, t.n_kc, p->J, ld, 1, p->Jn[ns - 1], p->dims[ns - 1],
+                                  ns - 1, 1, nullptr, last ? (float*)Gall[0] : (float*)p->chain[0], last ? R : ld};
+        }
+        if (tail && N - ns >= 2) {
+            // left (eq. 3.22): out(t, r) = sum_i Z(i + I t, r) A^(n*+1)(i, r), I = I_{n*+1};
+            // G^(N) itself when n* = N - 2
+            const bool last = ns + 2 == N;
+            sd[n++] = ReduceFirst{(const float*)p->PLpart, t.n_jr, p->K, ld, 0, p->Kn[ns + 1], p->dims[ns],
+                                  ns, 1, nullptr, last ? (float*)Gall[N - 1] : (float*)p->chain[2], last ? R : ld};
+        }
+        CPG_TRY(launch_reduce_first(sd, n, kr_gen(p, *fs), grams ? p->grams : nullptr, p->stream));
     }
     if ((roles & 1) && !fr) CPG_TRY(launch_reduce_parts(p->fdt, p->PRpart, t.n_kc, p->J, p->ld, p->PR, p->stream));
     if ((roles & 2) && !fl) CPG_TRY(launch_reduce_parts(p->fdt, p->PLpart, t.n_jr, p->K, p->ld, p->PL, p->stream));
@@ -445,28 +464,13 @@ static int run_side(cpgrad_plan_s* p, const FacSet<TC>& fs, int side, void* cons
     return CPG_OK;
 }
 
-// All-mode gradient after the fused reduction (G^(n*), G^(n*+1) written):
-// the first chain step of each side on many blocks, writing the next mode's
-// gradient directly when its Khatri-Rao block is empty; the single-block
-// epilogue only for modes left after that.
-static int all_modes_tail(cpgrad_plan_s* p, const FacSet<float>& fs, void* const* A, void* const* G) {
+// All-mode gradient after the fused reduction, which wrote G^(n*), G^(n*+1)
+// and the first chain step of each side (the next mode's gradient, or the
+// chain buffer when modes are left): the single-block epilogue for the modes
+// left after that.
+static int all_modes_tail(cpgrad_plan_s* p, const FacSet<float>& fs, void* const* G) {
     const int N = p->N, ns = p->nstar;
-    TtvFirst tf[2];
-    int nt = 0;
-    bool right_more = false, left_more = false;
-    if (ns >= 2) {
-        const bool last = ns == 2;   // G^(1) = R^(1)
-        tf[nt++] = TtvFirst{(const float*)p->PR, p->ld, 0, p->dims[ns - 1], p->Jn[ns - 1], (const float*)A[ns - 1],
-                            last ? (float*)G[0] : (float*)p->chain[0], last ? p->R : p->ld};
-        right_more = !last;
-    }
-    if (N - ns >= 2) {
-        const bool last = ns + 2 == N;   // G^(N) = L^(N)
-        tf[nt++] = TtvFirst{(const float*)p->PL, p->ld, 1, p->dims[ns], p->Kn[ns + 1], (const float*)A[ns],
-                            last ? (float*)G[N - 1] : (float*)p->chain[2], last ? p->R : p->ld};
-        left_more = !last;
-    }
-    if (nt) CPG_TRY(launch_ttv_first(tf, nt, p->R, p->stream));
+    const bool right_more = ns > 2, left_more = N - ns > 2;
     EpiArgs<float> a[2];
     int na = 0;
     if (right_more) {
@@ -877,12 +881,13 @@ int cpgrad_all_modes(cpgrad_plan_t p, const void* Y, const void* const* A, void*
     const AnyFacSet fs = facsets(p, A);
     CPG_TRY(run_contract(p, Y, fs, p->t_fused, 3));
     bool pre = false;
+    const bool tail = p->fdt == CPG_F32 && epilogue_fits(p);
     int st = finish_partials(p, p->fdt == CPG_F32 ? &fs.f : nullptr, p->t_fused, 3, G[p->nstar - 1], G[p->nstar],
-                             false, &pre);
+                             false, &pre, tail ? G : nullptr);
     if (st) return st;
     if (epilogue_fits(p)) {
         if (p->fdt == CPG_F64) return run_both_sides<double>(p, fs.d, (void* const*)A, G);
-        if (pre) return all_modes_tail(p, fs.f, (void* const*)A, G);
+        if (pre) return all_modes_tail(p, fs.f, G);
         return run_both_sides<float>(p, fs.f, (void* const*)A, G);
     }
     st = right_chain(p, fs, (void* const*)A, G, false);

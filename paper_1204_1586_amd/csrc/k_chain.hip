@@ -62,35 +62,49 @@ hipError_t launch_reduce_parts(int fdt, const void* parts, int64_t nparts, int64
 }
 
 // ---------------------------------------------------------------------------
-// Partial reduction fused with the gradient of the side's first mode.  Block
-// i < I of a side reduces the chain-tensor rows of output row i over the
-// split partials (float64, fixed order p = 0, 1, ...), stores them rounded to
-// float32, and forms from the stored values
-//   right (eq. 3.12): G(i, r) = sum_t Z(t + T i, r) KRs(t, r),  T = J_{n-1}
-//   left  (eq. 3.16): G(i, r) = sum_t Z(i + I t, r) KRs(t, r),  T = K_n
-// with KRs the float64 Khatri-Rao rows of the side's remaining modes, formed
-// from the factors in place.  Extra blocks (one per mode) compute the float64
+// Fused partial reduction.  Block i of a side reduces the chain-tensor rows of
+// its output row i over the split partials (float64, fixed order p = 0, 1, ...),
+// rounds them to float32 (stored as P_R / P_L when Z is set) and forms from
+// the rounded values
+//   G(i, r) = sum_t Z(row(i, t), r) KR(t, r)
+// with KR the float64 Khatri-Rao rows of the side's weighting modes, formed
+// from the factors in place.  Weighted by the side's remaining modes this is
+// its first gradient (right: eq. 3.12, rows t + T i; left: eq. 3.16, rows
+// i + I t); weighted by one mode it is the side's first chain step (eqs. 3.20 /
+// 3.22), read straight from the partials so that it needs no launch of its
+// own after the reduction.  Extra blocks (one per mode) compute the float64
 // Grams when `grams` is set.
 // ---------------------------------------------------------------------------
 constexpr int kRfBatch = 16;   // partial loads in flight per thread
 
-__device__ __forceinline__ void reduce_first_rows(const ReduceFirst& a, int64_t i, const KrGen& kg, d4s* spart) {
+__device__ __forceinline__ void reduce_first_rows(const ReduceFirst& a, int64_t blk, const KrGen& kg, d4s* spart) {
     const int R = kg.R;
     const int tid = threadIdx.x;
     const int ld = a.ld;
     const int nq = ld >> 2;                 // float4 columns of a row
     int nqp = 1;
     while (nqp < nq) nqp <<= 1;             // threads per term (a power of two <= 16)
+    const int rpb = rf_rows_per_block(a.side, ld);
     const int q = tid & (nqp - 1);
-    const int tslot = tid / nqp;
-    const int tstep = 256 / nqp;
+    const int sub = (tid / nqp) & (rpb - 1);  // output row of the block this thread serves
+    const int tslot = tid / (nqp * rpb);
+    const int tstep = 256 / (nqp * rpb);
+    const int64_t i = blk * rpb + sub;
     const int64_t rstride = a.side == 0 ? 1 : a.I;            // row of term t: rbase + t * rstride
     const int64_t rbase = a.side == 0 ? a.T * i : i;
     const int64_t pstride = a.rows * ld;                      // floats per partial
+    const int np = (int)a.nparts;
     d4s g{0.0, 0.0, 0.0, 0.0};
-    if (q < nq) {
+    if (q < nq && i < a.I) {
         for (int64_t t = tslot; t < a.T; t += tstep) {
             const int64_t row = rbase + t * rstride;
+            const float* src = a.parts + row * ld + 4 * q;
+            // The first batch of partials goes out before the factor loads of the
+            // weights (it does not depend on them), so both arrive in one round
+            // trip; slots past nparts re-read the last partial and are not added.
+            float4 v[kRfBatch];
+#pragma unroll
+            for (int u = 0; u < kRfBatch; ++u) v[u] = *(const float4*)(src + (int64_t)min(u, np - 1) * pstride);
             // weights: float64 Khatri-Rao row t of modes kr_first.. (Notation 2.1 order), zero past R
             double w[4];
 #pragma unroll
@@ -107,7 +121,6 @@ __device__ __forceinline__ void reduce_first_rows(const ReduceFirst& a, int64_t 
 #pragma unroll
                 for (int u = 0; u < 4; ++u) w[u] *= (double)x[u];
             }
-            const float* src = a.parts + row * ld + 4 * q;
             d4s acc{0.0, 0.0, 0.0, 0.0};
             auto add = [&](const float4& v) {
                 acc.x += (double)v.x;
@@ -115,27 +128,30 @@ __device__ __forceinline__ void reduce_first_rows(const ReduceFirst& a, int64_t 
                 acc.z += (double)v.z;
                 acc.w += (double)v.w;
             };
-            // full batches without branches (so the loads stay in flight together), then the tail
-            int64_t p = 0;
-            for (; p + kRfBatch <= a.nparts; p += kRfBatch) {
-                float4 v[kRfBatch];
+#pragma unroll
+            for (int u = 0; u < kRfBatch; ++u)
+                if (u < np) add(v[u]);
+            // further full batches without branches, then the tail
+            int p = kRfBatch;
+            for (; p + kRfBatch <= np; p += kRfBatch) {
 #pragma unroll
                 for (int u = 0; u < kRfBatch; ++u) v[u] = *(const float4*)(src + (p + u) * pstride);
 #pragma unroll
                 for (int u = 0; u < kRfBatch; ++u) add(v[u]);
             }
-            for (; p < a.nparts; ++p) add(*(const float4*)(src + p * pstride));
+            for (; p < np; ++p) add(*(const float4*)(src + p * pstride));
             const float4 z{(float)acc.x, (float)acc.y, (float)acc.z, (float)acc.w};
-            *(float4*)(a.Z + row * ld + 4 * q) = z;
+            if (a.Z) *(float4*)(a.Z + row * ld + 4 * q) = z;
             g.x += (double)z.x * w[0];
             g.y += (double)z.y * w[1];
             g.z += (double)z.z * w[2];
             g.w += (double)z.w * w[3];
         }
     }
+    // sum over the term slots (fixed tree order); slot 0 of (sub, q) ends in spart[sub * nqp + q]
     spart[tid] = g;
     __syncthreads();
-    for (int st = 128; st >= nqp; st >>= 1) {
+    for (int st = 128; st >= nqp * rpb; st >>= 1) {
         if (tid < st) {
             spart[tid].x += spart[tid + st].x;
             spart[tid].y += spart[tid + st].y;
@@ -144,142 +160,111 @@ __device__ __forceinline__ void reduce_first_rows(const ReduceFirst& a, int64_t 
         }
         __syncthreads();
     }
-    if (tid < nq) {
+    if (tid < nqp * rpb && q < nq && i < a.I) {
         const d4s v = spart[tid];
         const double vv[4] = {v.x, v.y, v.z, v.w};
+        float* out = a.G + i * a.out_ld + 4 * q;
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (4 * tid + u < R) a.G[i * R + 4 * tid + u] = (float)vv[u];
+        for (int u = 0; u < 4; ++u) {
+            const int r = 4 * q + u;
+            if (r < R)
+                out[u] = (float)vv[u];
+            else if (r < a.out_ld)
+                out[u] = 0.f;   // padding columns of a chain buffer
+        }
     }
 }
 
-__global__ __launch_bounds__(256) void k_reduce_first(ReduceFirst s0, ReduceFirst s1, int64_t nb0, int64_t nb1,
-                                                      KrGen kg, double* __restrict__ grams) {
+struct RfSides {
+    ReduceFirst s[kMaxReduceSides];
+    int64_t first[kMaxReduceSides + 1];   // first block of each side; first[n]: blocks of all sides
+    int n;
+};
+
+__global__ __launch_bounds__(256) void k_reduce_first(RfSides sd, KrGen kg, double* __restrict__ grams) {
     __shared__ d4s spart[256];
     const int64_t b = blockIdx.x;
-    if (b < nb0) {
-        reduce_first_rows(s0, b, kg, spart);
-    } else if (b < nb0 + nb1) {
-        reduce_first_rows(s1, b - nb0, kg, spart);
+    if (b < sd.first[sd.n]) {
+        int k = 0;
+        while (k + 1 < sd.n && b >= sd.first[k + 1]) ++k;
+        reduce_first_rows(sd.s[k], b - sd.first[k], kg, spart);
     } else {
-        // float64 Gram of mode m, terms in index order
-        const int m = (int)(b - nb0 - nb1);
+        // float64 Gram of mode m, terms in index order; the factor is staged
+        // through LDS in chunks of whole rows (one round trip per chunk)
+        const int m = (int)(b - sd.first[sd.n]);
         if (grams == nullptr || m >= kg.N) return;
         const int R = kg.R;
+        const int tid = threadIdx.x;
         const float* A = kg.A[m];
         const int64_t I = kg.fd[m].d;
-        for (int e = threadIdx.x; e < R * R; e += 256) {
-            const int r = e / R, c = e - (e / R) * R;
-            double acc = 0.0;
-            int64_t i = 0;
-            for (; i + 8 <= I; i += 8) {   // terms in index order; loads of 8 rows at a time
-                float vr[8], vc[8];
+        constexpr int kChunk = 2048;                 // floats: the 256 float4 of spart
+        constexpr int kPer = kChunk / 256;
+        constexpr int kGrp = 4;                      // Gram entries per thread and pass
+        float* sA = reinterpret_cast<float*>(spart);
+        const int64_t rows_per = kChunk / R;
+        for (int e0 = 0; e0 < R * R; e0 += 256 * kGrp) {
+            double acc[kGrp];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    vr[u] = A[(i + u) * R + r];
-                    vc[u] = A[(i + u) * R + c];
+            for (int k = 0; k < kGrp; ++k) acc[k] = 0.0;
+            for (int64_t i0 = 0; i0 < I; i0 += rows_per) {
+                const int nf = (int)(min(rows_per, I - i0) * R);
+                float v[kPer];
+#pragma unroll
+                for (int u = 0; u < kPer; ++u) v[u] = A[i0 * R + min(tid + 256 * u, nf - 1)];
+                __syncthreads();   // the previous chunk is consumed
+#pragma unroll
+                for (int u = 0; u < kPer; ++u)
+                    if (tid + 256 * u < nf) sA[tid + 256 * u] = v[u];
+                __syncthreads();
+                const int nr = nf / R;
+#pragma unroll
+                for (int k = 0; k < kGrp; ++k) {
+                    const int e = e0 + tid + 256 * k;
+                    if (e < R * R) {
+                        const int r = e / R, c = e - (e / R) * R;
+                        int ii = 0;
+                        for (; ii + 8 <= nr; ii += 8) {   // eight rows of LDS reads in flight
+                            float xr[8], xc[8];
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) {
+                                xr[u] = sA[(ii + u) * R + r];
+                                xc[u] = sA[(ii + u) * R + c];
+                            }
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) acc[k] += (double)xr[u] * (double)xc[u];
+                        }
+                        for (; ii < nr; ++ii) acc[k] += (double)sA[ii * R + r] * (double)sA[ii * R + c];
+                    }
                 }
-#pragma unroll
-                for (int u = 0; u < 8; ++u) acc += (double)vr[u] * (double)vc[u];
             }
-            for (; i < I; ++i) acc += (double)A[i * R + r] * (double)A[i * R + c];
-            grams[(int64_t)m * R * R + e] = acc;
+#pragma unroll
+            for (int k = 0; k < kGrp; ++k) {
+                const int e = e0 + tid + 256 * k;
+                if (e < R * R) grams[(int64_t)m * R * R + e] = acc[k];
+            }
         }
     }
 }
 
 hipError_t launch_reduce_first(const ReduceFirst* sides, int nsides, const KrGen& kg, double* grams,
                                hipStream_t s) {
-    if (nsides < 1 || nsides > 2) return hipErrorInvalidValue;
-    for (int k = 0; k < nsides; ++k)
-        if ((sides[k].ld & 3) != 0 || sides[k].ld > 64) return hipErrorInvalidValue;
-    const int64_t nb0 = sides[0].I, nb1 = nsides > 1 ? sides[1].I : 0;
-    const int64_t nb = nb0 + nb1 + (grams ? kg.N : 0);
-    hipLaunchKernelGGL(k_reduce_first, dim3((unsigned)nb), dim3(256), 0, s, sides[0], sides[nsides - 1], nb0, nb1,
-                       kg, grams);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// First chain step of each side for the all-mode gradient (no updates), many
-// blocks: the chain tensor after the side's first mode,
-//   right (eq. 3.20): out(t, r) = sum_i Z(t + T i, r) A(i, r),  T = J_{n*-1}, A = A^(n*)
-//   left  (eq. 3.22): out(t, r) = sum_i Z(i + I t, r) A(i, r),  T = K_{n*+1}, A = A^(n*+1)
-// written with row stride out_ld (ld for a chain buffer, R when it is already
-// the next mode's gradient).  Each output float4 is summed by kTfParts threads
-// over interleaved terms, the parts added in fixed order.
-// ---------------------------------------------------------------------------
-constexpr int kTfParts = 16;
-constexpr int kTfOut = 256 / kTfParts;   // outputs (float4) per block
-
-__device__ __forceinline__ void ttv_first_rows(const TtvFirst& a, int64_t blk, int R, d4s* spart) {
-    const int tid = threadIdx.x;
-    const int ol = tid % kTfOut, part = tid / kTfOut;
-    const int nq = a.ld >> 2;
-    const int64_t o = blk * kTfOut + ol;
-    const bool live = o < a.T * nq;
-    const int64_t t = live ? o / nq : 0;
-    const int q = live ? (int)(o - t * nq) : 0;
-    const int64_t rstride = a.side == 0 ? a.T : 1;      // row of term i: rbase + i * rstride
-    const int64_t rbase = a.side == 0 ? t : a.I * t;
-    const float* src = a.Z + rbase * a.ld + 4 * q;
-    const int64_t zstep = rstride * a.ld;
-    int rr[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) rr[u] = min(4 * q + u, R - 1);   // factor column (clamped in the padding)
-    d4s acc{0.0, 0.0, 0.0, 0.0};
-    auto add = [&](const float4& z, int64_t i) {
-        const float* w = a.A + i * R;
-        acc.x += (double)z.x * (double)w[rr[0]];
-        acc.y += (double)z.y * (double)w[rr[1]];
-        acc.z += (double)z.z * (double)w[rr[2]];
-        acc.w += (double)z.w * (double)w[rr[3]];
-    };
-    int64_t i = part;
-    for (; i + 3 * kTfParts < a.I; i += 4 * kTfParts) {   // four terms in flight
-        float4 z[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) z[u] = *(const float4*)(src + (i + u * kTfParts) * zstep);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) add(z[u], i + u * kTfParts);
-    }
-    for (; i < a.I; i += kTfParts) add(*(const float4*)(src + i * zstep), i);
-    spart[tid] = live ? acc : d4s{0.0, 0.0, 0.0, 0.0};
-    __syncthreads();
-    if (part == 0 && live) {
-        d4s v = spart[ol];
-        for (int p = 1; p < kTfParts; ++p) {
-            const d4s w = spart[p * kTfOut + ol];
-            v.x += w.x;
-            v.y += w.y;
-            v.z += w.z;
-            v.w += w.w;
-        }
-        const double vv[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (a.out_ld != R || 4 * q + u < R) a.out[t * a.out_ld + 4 * q + u] = (4 * q + u < R) ? (float)vv[u] : 0.f;
-    }
-}
-
-__global__ __launch_bounds__(256) void k_ttv_first(TtvFirst s0, TtvFirst s1, int64_t nb0, int64_t nb1, int R) {
-    __shared__ d4s spart[256];
-    const int64_t b = blockIdx.x;
-    if (b < nb0)
-        ttv_first_rows(s0, b, R, spart);
-    else if (b < nb0 + nb1)
-        ttv_first_rows(s1, b - nb0, R, spart);
-}
-
-hipError_t launch_ttv_first(const TtvFirst* sides, int nsides, int R, hipStream_t s) {
-    if (nsides < 1 || nsides > 2) return hipErrorInvalidValue;
-    int64_t nb[2] = {0, 0};
+    if (nsides < 1 || nsides > kMaxReduceSides) return hipErrorInvalidValue;
+    RfSides sd{};
+    sd.n = nsides;
+    int64_t nb = 0;
     for (int k = 0; k < nsides; ++k) {
-        if ((sides[k].ld & 3) != 0) return hipErrorInvalidValue;
-        nb[k] = (sides[k].T * (sides[k].ld >> 2) + kTfOut - 1) / kTfOut;
+        const ReduceFirst& a = sides[k];
+        if ((a.ld & 3) != 0 || a.ld > 64 || a.nparts < 1 || (a.out_ld != kg.R && a.out_ld != a.ld))
+            return hipErrorInvalidValue;
+        sd.s[k] = a;
+        sd.first[k] = nb;
+        const int rpb = rf_rows_per_block(a.side, a.ld);
+        nb += (a.I + rpb - 1) / rpb;
     }
-    hipLaunchKernelGGL(k_ttv_first, dim3((unsigned)(nb[0] + nb[1])), dim3(256), 0, s, sides[0], sides[nsides - 1],
-                       nb[0], nb[1], R);
+    sd.first[nsides] = nb;
+    const int64_t total = nb + (grams ? kg.N : 0);
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_first, dim3((unsigned)total), dim3(256), 0, s, sd, kg, grams);
     return hipGetLastError();
 }
 

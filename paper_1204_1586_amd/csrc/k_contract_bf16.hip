@@ -153,8 +153,9 @@ __global__ __launch_bounds__(256) void k_contract_bf16(const void* __restrict__ 
     // mode j of the left product and mode n*+j of the right one.
     v8us krl_hi[DO_L ? 2 : 1][DO_L ? NRT : 1], krl_lo[DO_L && KLO ? 2 : 1][DO_L && KLO ? NRT : 1];
     constexpr int kKrBatch = 8;
+    constexpr int kPeel = NRT <= 2 ? 2 : 1;   // Khatri-Rao rounds whose loads precede the first Y loads
     const int n4 = (int)(nsteps * kB16Step) * (RT / 4);
-    auto gen_kr = [&](int base, bool with_left) {
+    auto gen_kr = [&](int base, bool with_left, auto&& mid) {
         float fl[DO_L ? NRT : 1][16];
         uint32_t idxL[16], idxR[kKrBatch];
         int r4[kKrBatch];
@@ -184,9 +185,10 @@ __global__ __launch_bounds__(256) void k_contract_bf16(const void* __restrict__ 
         const int nL = (DO_L && with_left) ? kg.nstar : 0;
         const int nR = DO_R ? kg.N - kg.nstar : 0;
         const int rounds = nL > nR ? nL : nR;
-        for (int j = 0; j < rounds; ++j) {
+        // factor loads of round j (a mode past a side's count reads zero here and
+        // multiplies by one below)
+        auto issue = [&](int j, float (&vl)[DO_L ? NRT : 1][16], float (&vr)[DO_R ? kKrBatch : 1][4]) {
             const bool aL = j < nL, aR = j < nR;
-            float vl[DO_L ? NRT : 1][16], vr[DO_R ? kKrBatch : 1][4];
             if (DO_L && with_left) {
                 const int m = aL ? j : 0;
                 const FastDiv f = kg.fd[m];
@@ -221,6 +223,9 @@ __global__ __launch_bounds__(256) void k_contract_bf16(const void* __restrict__ 
                     }
                 }
             }
+        };
+        auto consume = [&](int j, const float (&vl)[DO_L ? NRT : 1][16], const float (&vr)[DO_R ? kKrBatch : 1][4]) {
+            const bool aL = j < nL, aR = j < nR;
             if (DO_L && with_left) {
 #pragma unroll
                 for (int rt = 0; rt < NRT; ++rt)
@@ -233,6 +238,23 @@ __global__ __launch_bounds__(256) void k_contract_bf16(const void* __restrict__ 
 #pragma unroll
                     for (int c = 0; c < 4; ++c) t[u][c] *= aR ? vr[u][c] : 1.f;
             }
+        };
+        // The first kPeel rounds are issued before `mid` (the first steps of Y
+        // on the first chunk), so that waiting for them does not wait for Y as
+        // well (loads complete in order for the wait counter); later rounds, if
+        // any, load and multiply in turn.
+        float vlp[kPeel][DO_L ? NRT : 1][16], vrp[kPeel][DO_R ? kKrBatch : 1][4];
+#pragma unroll
+        for (int j = 0; j < kPeel; ++j) issue(j, vlp[j], vrp[j]);
+        __builtin_amdgcn_sched_barrier(0);
+        mid();
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int j = 0; j < kPeel; ++j) consume(j, vlp[j], vrp[j]);
+        for (int j = kPeel; j < rounds; ++j) {
+            float vl[DO_L ? NRT : 1][16], vr[DO_R ? kKrBatch : 1][4];
+            issue(j, vl, vr);
+            consume(j, vl, vr);
         }
         if (DO_L && with_left) {
 #pragma unroll
@@ -385,10 +407,12 @@ __global__ __launch_bounds__(256) void k_contract_bf16(const void* __restrict__ 
     // Prologue: the first steps of Y go out first, then the Khatri-Rao rows.
     constexpr int NB = kB16Depth + 1;
     Raw rbuf[NB];
+    gen_kr(0, true, [&] {
 #pragma unroll
-    for (int d = 0; d < kB16Depth; ++d) load_step(rbuf[d], d);
-    gen_kr(0, true);
-    for (int base = kKrBatch * 256; DO_R && base < n4; base += kKrBatch * 256) gen_kr(base, false);   // wide chunks
+        for (int d = 0; d < kB16Depth; ++d) load_step(rbuf[d], d);
+    });
+    for (int base = kKrBatch * 256; DO_R && base < n4; base += kKrBatch * 256)   // wide chunks
+        gen_kr(base, false, [] {});
     lds_block_sync_b();
 
     for (int64_t st = 0; st < nsteps; st += NB) {

@@ -75,12 +75,13 @@ __global__ __launch_bounds__(256) void k_contract_mfma_f32(const float* __restri
     const int64_t nsteps = (gsteps - blockIdx.y + n_kc - 1) / n_kc;
     auto step_col = [&](int64_t st) { return (st * n_kc + blockIdx.y) * kStep; };   // first column of step st
 
-    // Prologue.  The first steps of Y are issued first; meanwhile the block's
-    // Khatri-Rao rows (eq. 3.3, Notation 2.1 order: the first mode of a
-    // product fastest) are generated from the factors: row indices unravel
-    // into per-mode indices by multiply-shift division, one round of factor
-    // loads per mode; factor entries past R read as zero (buffer loads, no
-    // branches).  Products are formed in float32 in mode order.
+    // Prologue.  The block's Khatri-Rao rows (eq. 3.3, Notation 2.1 order: the
+    // first mode of a product fastest) are generated from the factors: row
+    // indices unravel into per-mode indices by multiply-shift division, one
+    // round of factor loads per mode; factor entries past R read as zero
+    // (buffer loads, no branches).  Products are formed in float32 in mode
+    // order.  The first steps of Y are issued right after the factor loads of
+    // the first rounds, so they are in flight while the rows are formed.
     const int R = kg.R;
     auto fac_rsrc = [&](int m) { return buf_rsrc(kg.A[m], (uint32_t)(kg.fd[m].d * (uint32_t)R * 4)); };
     //
@@ -89,6 +90,7 @@ __global__ __launch_bounds__(256) void k_contract_mfma_f32(const float* __restri
     // KR_R rows of the block's steps (LDS row st*32 + kk <- column step_col(st) + kk),
     // four ranks per entry; rows past K and ranks past R are zero
     constexpr int kKrBatch = 8;
+    constexpr int kPeel = NRT <= 2 ? 2 : 1;   // Khatri-Rao rounds whose loads precede the first Y loads
     const int n4 = (int)(nsteps * kStep) * (RT / 4);
     auto load_krr = [&](v4f (&t)[kKrBatch], int base) {
         uint32_t idx[kKrBatch];
@@ -124,7 +126,7 @@ __global__ __launch_bounds__(256) void k_contract_mfma_f32(const float* __restri
     // First batch of KR_R rows and the KR_L rows together: round j loads mode j
     // of the left product and mode n*+j of the right one, so the rounds are
     // max(n*, N-n*) (a mode past a side's count multiplies by one).
-    auto gen_first = [&](v4f (&t)[kKrBatch]) {
+    auto gen_first = [&](v4f (&t)[kKrBatch], auto&& mid) {
         uint32_t idxL[16], idxR[kKrBatch];
         int r4[kKrBatch];
         if (DO_L) {
@@ -152,9 +154,10 @@ __global__ __launch_bounds__(256) void k_contract_mfma_f32(const float* __restri
         const int nL = DO_L ? kg.nstar : 0;
         const int nR = DO_R ? kg.N - kg.nstar : 0;
         const int rounds = nL > nR ? nL : nR;
-        for (int j = 0; j < rounds; ++j) {
+        // factor loads of round j (a mode past a side's count reads zero here and
+        // multiplies by one below)
+        auto issue = [&](int j, float (&vl)[DO_L ? NRT : 1][16], float (&vr)[DO_R ? kKrBatch : 1][4]) {
             const bool aL = j < nL, aR = j < nR;
-            float vl[DO_L ? NRT : 1][16], vr[DO_R ? kKrBatch : 1][4];
             if (DO_L) {
                 const int m = aL ? j : 0;
                 const FastDiv f = kg.fd[m];
@@ -189,6 +192,9 @@ __global__ __launch_bounds__(256) void k_contract_mfma_f32(const float* __restri
                     }
                 }
             }
+        };
+        auto consume = [&](int j, const float (&vl)[DO_L ? NRT : 1][16], const float (&vr)[DO_R ? kKrBatch : 1][4]) {
+            const bool aL = j < nL, aR = j < nR;
             if (DO_L) {
 #pragma unroll
                 for (int rt = 0; rt < NRT; ++rt)
@@ -201,6 +207,22 @@ __global__ __launch_bounds__(256) void k_contract_mfma_f32(const float* __restri
 #pragma unroll
                     for (int c = 0; c < 4; ++c) t[u][c] *= aR ? vr[u][c] : 1.f;
             }
+        };
+        // The first kPeel rounds are issued before the first steps of Y, so that
+        // waiting for them does not wait for Y as well (loads complete in order
+        // for the wait counter); later rounds, if any, load and multiply in turn.
+        float vlp[kPeel][DO_L ? NRT : 1][16], vrp[kPeel][DO_R ? kKrBatch : 1][4];
+#pragma unroll
+        for (int j = 0; j < kPeel; ++j) issue(j, vlp[j], vrp[j]);
+        __builtin_amdgcn_sched_barrier(0);
+        mid();
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int j = 0; j < kPeel; ++j) consume(j, vlp[j], vrp[j]);
+        for (int j = kPeel; j < rounds; ++j) {
+            float vl[DO_L ? NRT : 1][16], vr[DO_R ? kKrBatch : 1][4];
+            issue(j, vl, vr);
+            consume(j, vl, vr);
         }
     };
     auto store_krr = [&](const v4f (&t)[kKrBatch], int base) {
@@ -321,11 +343,12 @@ __global__ __launch_bounds__(256) void k_contract_mfma_f32(const float* __restri
     // so the loads of the kDepth steps ahead stay in flight)
     constexpr int NB = kDepth + 1;
     v4f buf[NB][8];
-#pragma unroll
-    for (int d = 0; d < kDepth; ++d) load_step(buf[d], d);
     {
         v4f krt[kKrBatch];
-        gen_first(krt);
+        gen_first(krt, [&] {
+#pragma unroll
+            for (int d = 0; d < kDepth; ++d) load_step(buf[d], d);
+        });
         if (DO_R) store_krr(krt, 0);
         for (int base = kKrBatch * 256; DO_R && base < n4; base += kKrBatch * 256) {  // wide chunks only
             load_krr(krt, base);
