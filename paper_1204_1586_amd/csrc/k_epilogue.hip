@@ -316,119 +316,6 @@ __device__ __forceinline__ void block_grams_all(const FacSet<TC>& fs, double* gr
     }
 }
 
-// eq. 2.14 for mode n (0-based) with G^(n) in sG, wide rank tiles: A^(n) <- G Gamma^{-1} by a
-// float64 Cholesky factorisation Gamma = L L^T (right-looking, one block
-// barrier per column; one retry with Gamma + 1e-12 tr(Gamma)/R I) and, for
-// every row g of G, the two triangular solves L z = g^T, L^T x = z.  Returns
-// false (leaving A^(n) and grams[n] untouched) if Gamma is not SPD.
-template <typename TC, int RT>
-__device__ __forceinline__ bool block_solve_lds(const EpiArgs<TC>& a, int n, const double* sG, double* sGam, double* sL,
-                                            double* sA, double* spart, int* sOk) {
-    constexpr int LD = RT + 1;
-    const int tid = threadIdx.x;
-    const int R = a.fs.R;
-    const int N = a.fs.N;
-    const int64_t I = a.fs.dims[n];
-    for (int e = tid; e < R * R; e += kEpiThreads) {
-        double g[CPG_MAX_MODES];
-#pragma unroll
-        for (int k = 0; k < CPG_MAX_MODES; ++k) g[k] = (k < N && k != n) ? a.grams[(int64_t)k * R * R + e] : 1.0;
-        double v = 1.0;
-#pragma unroll
-        for (int k = 0; k < CPG_MAX_MODES; ++k) v *= g[k];
-        sGam[e] = v;
-    }
-    __syncthreads();
-    CPG_EPI_MARK(20);
-    double tr = 0.0;
-    for (int c = 0; c < R; ++c) tr += sGam[c * R + c];
-    bool good = false;
-    for (int attempt = 0; attempt < 2 && !good; ++attempt) {
-        const double jit = attempt == 0 ? 0.0 : 1e-12 * tr / R;
-        for (int e = tid; e < R * R; e += kEpiThreads) {
-            const int i = e / R, j = e - (e / R) * R;
-            sL[i * LD + j] = sGam[e] + (i == j ? jit : 0.0);
-        }
-        __syncthreads();
-        bool bad = false;
-        // column c: trailing update a_ij -= a_ic a_jc / a_cc (c < j <= i), one barrier
-        for (int c = 0; c < R; ++c) {
-            const double d = sL[c * LD + c];
-            bad = bad || !(d > 0.0) || !isfinite(d);
-            const double inv = bad ? 0.0 : 1.0 / d;
-            const int m = R - 1 - c;
-            for (int e = tid; e < m * m; e += kEpiThreads) {
-                const int i = c + 1 + e / m, j = c + 1 + (e - (e / m) * m);
-                if (j <= i) sL[i * LD + j] -= sL[i * LD + c] * sL[j * LD + c] * inv;
-            }
-            __syncthreads();
-        }
-        good = !bad;
-        if (good) {
-            // scale the columns: L_ic = a_ic / sqrt(a_cc); keep 1/L_cc on the diagonal
-            for (int e = tid; e < R * R; e += kEpiThreads) {
-                const int i = e / R, c = e - (e / R) * R;
-                if (i > c) sL[i * LD + c] = sL[i * LD + c] / sqrt(sL[c * LD + c]);
-            }
-            __syncthreads();
-            for (int c = tid; c < R; c += kEpiThreads) sL[c * LD + c] = 1.0 / sqrt(sL[c * LD + c]);
-            __syncthreads();
-        }
-    }
-    CPG_EPI_MARK(21);
-    if (!good) return false;
-    // W = L^{-1}, one row per step: w_ij = (delta_ij - sum_{j<=k<i} L_ik w_kj) / L_ii  (W in sGam)
-    for (int i = 0; i < R; ++i) {
-        for (int j = tid; j <= i; j += kEpiThreads) {
-            double v = (i == j) ? 1.0 : 0.0;
-            for (int k = j; k < i; ++k) v -= sL[i * LD + k] * sGam[k * RT + j];
-            sGam[i * RT + j] = v * sL[i * LD + i];
-        }
-        __syncthreads();
-    }
-    // Gamma^{-1} = W^T W (W lower triangular) -> sL (stride LD); L is no longer needed
-    for (int e = tid; e < R * R; e += kEpiThreads) {
-        const int r = e / R, c = e - (e / R) * R;
-        double acc = 0.0;
-        for (int i = (r > c ? r : c); i < R; ++i) acc += sGam[i * RT + r] * sGam[i * RT + c];
-        sL[r * LD + c] = acc;
-    }
-    __syncthreads();
-    // A^(n) = G Gamma^{-1}
-    TC* A = (TC*)a.fs.A[n];
-    for (int64_t o = tid; o < I * R; o += kEpiThreads) {
-        const int64_t i = o / R;
-        const int c = (int)(o - i * R);
-        double a0 = 0.0, a1 = 0.0;
-        int s = 0;
-        for (; s + 2 <= R; s += 2) {
-            a0 += sG[i * RT + s] * sL[s * LD + c];
-            a1 += sG[i * RT + s + 1] * sL[(s + 1) * LD + c];
-        }
-        if (s < R) a0 += sG[i * RT + s] * sL[s * LD + c];
-        const TC v = (TC)(a0 + a1);
-        A[o] = v;
-        sA[o] = (double)v;   // the stored (rounded) factor, for its Gram
-    }
-    __syncthreads();
-    CPG_EPI_MARK(22);
-    CPG_EPI_MARK(23);
-    int64_t off0 = 0, In[CPG_MAX_MODES];
-    In[n] = I;
-    int64_t offs[CPG_MAX_MODES];
-    offs[n] = off0;
-    block_gram_staged(sA, offs, In, n, n + 1, R, a.grams, spart);
-    return true;
-}
-
-// 1/sqrt(d) in float64: hardware estimate refined by two Newton steps
-__device__ __forceinline__ double rsqrt_d(double d) {
-    double y = __builtin_amdgcn_rsq(d);
-    y = y * (1.5 - 0.5 * d * y * y);
-    y = y * (1.5 - 0.5 * d * y * y);
-    return y;
-}
-
 // Gamma (R x R, stride RT) = Hadamard product of the float64 Grams of every
 // mode but n (eq. 2.14).
 template <typename TC, int RT>
@@ -447,165 +334,292 @@ __device__ __forceinline__ void block_gamma(const EpiArgs<TC>& a, int n, double*
     }
 }
 
-// One wave: W = L^{-1} for Gamma = L L^T (Gamma in sGam, stride RT), written
-// to sW (stride RT, zero above the diagonal); rows and columns R..RT-1 are
-// padded with the identity.  Cholesky in the row (dot-product) form
-//   L_jj = sqrt(Gamma_jj - sum_{k<j} L_jk^2),
-//   L_ij = (Gamma_ij - sum_{k<j} L_ik L_jk) / L_jj          (i > j):
-// lane i keeps row i in registers and publishes each new entry L_ij to LDS
-// (sLs, stride RT; 1/L_jj after the RT x RT entries); at column j every lane
-// reads row j back as a broadcast and forms the pivot itself, so no lane
-// waits on another beyond the wave's in-order LDS traffic.  Then W column by
-// column, lane c independently:
-//   W_cc = 1/L_cc,  W_ic = -(sum_{c<=k<i} L_ik W_kc) / L_ii   (i > c),
-// with the rows of L read from LDS.  Returns false on a pivot that is not
-// positive and finite (uniform over the wave).
+// Gram of a solved factor held as rows of stride RT (float64): entry (r, c)
+// summed over rows i = h, h + g, ... by g threads, the g partial sums then
+// added in order h = 0, 1, ...
 template <int RT>
-__device__ __forceinline__ bool wave_chol_inverse(const double* sGam, int R, double jit, double* sLs, double* sW) {
-    // lane id read here (not hoistable): the lane masks of the unrolled
-    // columns then live only inside this function instead of the whole kernel
-    int l;
-    asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(l));
-    double* sDinv = sLs + RT * RT;
-    auto gam = [&](int i, int k) -> double {
-        return (i < R && k < R) ? sGam[i * RT + k] + (i == k ? jit : 0.0) : (i == k ? 1.0 : 0.0);
-    };
-    double x[RT], diag[RT];
+__device__ __forceinline__ void block_gram_rows(const double* X, int64_t I, int R, double* gout, double* spart) {
+    const int tid = threadIdx.x;
+    const int E = R * R;
+    if (E > kEpiThreads) {
+        for (int e = tid; e < E; e += kEpiThreads) {
+            const int r = e / R, c = e - (e / R) * R;
+            double s[4] = {0.0, 0.0, 0.0, 0.0};
+            int64_t i = 0;
+            for (; i + 3 < I; i += 4) {
 #pragma unroll
-    for (int k = 0; k < RT; ++k) {
-        x[k] = l < RT ? gam(l, k) : 0.0;
-        diag[k] = gam(k, k);
-    }
-    bool bad = false;
-    CPG_EPI_WMARK(0);
-#pragma unroll
-    for (int j = 0; j < RT; ++j) {
-        double Lj[j > 0 ? j : 1];
-#pragma unroll
-        for (int k = 0; k < j; ++k) Lj[k] = sLs[j * RT + k];
-        const double gjj = diag[j];
-        double sv[4] = {0.0, 0.0, 0.0, 0.0}, st[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int k = 0; k < j; ++k) {
-            sv[k & 3] += Lj[k] * Lj[k];
-            st[k & 3] += x[k] * Lj[k];
+                for (int u = 0; u < 4; ++u) s[u] += X[(i + u) * RT + r] * X[(i + u) * RT + c];
+            }
+            for (; i < I; ++i) s[0] += X[i * RT + r] * X[i * RT + c];
+            gout[e] = (s[0] + s[1]) + (s[2] + s[3]);
         }
-        const double v = gjj - ((sv[0] + sv[1]) + (sv[2] + sv[3]));
-        const double t = x[j] - ((st[0] + st[1]) + (st[2] + st[3]));
-        bad = bad || !(v > 0.0) || !isfinite(v);
-        const double y = rsqrt_d(v);
-        x[j] = l > j ? t * y : (l == j ? v * y : x[j]);
-        if (l >= j && l < RT) sLs[l * RT + j] = x[j];
-        if (l == j) sDinv[j] = y;
-        wave_lds_sync();
-        __builtin_amdgcn_sched_barrier(0);
+        __syncthreads();
+        return;
     }
-    CPG_EPI_WMARK(1);
-    if (bad) return false;
-    double wv[RT];
+    int g = 1;
+    while (g < 8 && 2 * g * E <= kEpiThreads) g *= 2;
+    double acc = 0.0;
+    if (tid < g * E) {
+        const int e = tid % E, h = tid / E;
+        const int r = e / R, c = e - (e / R) * R;
+        double s[4] = {0.0, 0.0, 0.0, 0.0};
+        int64_t i = h;
+        for (; i + 3 * g < I; i += 4 * g) {
 #pragma unroll
-    for (int i = 0; i < RT; ++i) {
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int k = 0; k < i; ++k) acc[k & 3] += sLs[i * RT + k] * wv[k];
-        const double di = sDinv[i];
-        wv[i] = l == i ? di : (l < i ? -((acc[0] + acc[1]) + (acc[2] + acc[3])) * di : 0.0);
-        __builtin_amdgcn_sched_barrier(0);   // one row of L in registers at a time
+            for (int u = 0; u < 4; ++u) s[u] += X[(i + u * g) * RT + r] * X[(i + u * g) * RT + c];
+        }
+        for (; i < I; i += g) s[0] += X[i * RT + r] * X[i * RT + c];
+        acc = (s[0] + s[1]) + (s[2] + s[3]);
     }
-    CPG_EPI_WMARK(2);
-    if (l < RT) {
-#pragma unroll
-        for (int i = 0; i < RT; ++i) sW[i * RT + l] = wv[i];
+    spart[tid] = acc;
+    __syncthreads();
+    if (tid < E) {
+        double v = spart[tid];
+        for (int h = 1; h < g; ++h) v += spart[h * E + tid];
+        gout[tid] = v;
     }
-    CPG_EPI_WMARK(3);
+    __syncthreads();
+}
+
+// 1/d in float64: hardware estimate refined by two Newton steps
+__device__ __forceinline__ double rcp_d(double d) {
+    double y = __builtin_amdgcn_rcp(d);
+    y = __builtin_fma(y, __builtin_fma(-d, y, 1.0), y);
+    y = __builtin_fma(y, __builtin_fma(-d, y, 1.0), y);
+    return y;
+}
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// Rank tiles up to 16: the elimination below in the registers of single
+// waves.  Lane l of a wave holds column l of Gamma' (lanes < R) and columns
+// i = 64 (8 q + w) + l of G^T; at step k the multipliers Gamma'_sk and the pivot
+// come from lane k by readlane, so a step needs no LDS and no barrier.  Every
+// wave with columns of G^T repeats the (small) elimination of Gamma', with
+// identical results.  *sFlag carries the outcome to the other waves.
+template <typename TC, int RT>
+__device__ __forceinline__ bool wave_eliminate(const EpiArgs<TC>& a, int n, const double* sG, const double* sGam,
+                                               double* sF, int* sFlag) {
+    constexpr int kSets = (kEpiGCap / RT + kEpiThreads - 1) / kEpiThreads;   // columns of G^T per lane
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    const int R = a.fs.R;
+    const int64_t I = a.fs.dims[n];
+    if ((int64_t)w * 64 < I) {
+        double gc[RT], xc[kSets][RT];
+#pragma unroll
+        for (int s = 0; s < RT; ++s) gc[s] = (l < R && s < R) ? sGam[s * RT + l] : 0.0;
+#pragma unroll
+        for (int q = 0; q < kSets; ++q) {
+            const int64_t i = (int64_t)(q * (kEpiThreads / 64) + w) * 64 + l;
+#pragma unroll
+            for (int s = 0; s < RT; ++s) xc[q][s] = (i < I && s < R) ? sG[i * RT + s] : 0.0;
+        }
+        bool ok = true;
+#pragma unroll
+        for (int k = 0; k < RT; ++k) {
+            if (k < R && ok) {
+                const double piv = readlane_d(gc[k], k);
+                if (!(piv > 0.0) || !isfinite(piv)) {
+                    ok = false;
+                } else {
+                    const double rp = rcp_d(piv);
+                    const double tg = gc[k] * rp;
+                    double tx[kSets];
+#pragma unroll
+                    for (int q = 0; q < kSets; ++q) tx[q] = xc[q][k] * rp;
+#pragma unroll
+                    for (int s = 0; s < RT; ++s) {
+                        if (s == k) continue;
+                        const double m = readlane_d(gc[s], k);   // Gamma'_sk
+                        gc[s] -= m * tg;
+#pragma unroll
+                        for (int q = 0; q < kSets; ++q) xc[q][s] -= m * tx[q];
+                    }
+                    gc[k] = tg;
+#pragma unroll
+                    for (int q = 0; q < kSets; ++q) xc[q][k] = tx[q];
+                }
+            }
+        }
+        if (ok) {
+            TC* A = (TC*)a.fs.A[n];
+#pragma unroll
+            for (int q = 0; q < kSets; ++q) {
+                const int64_t i = (int64_t)(q * (kEpiThreads / 64) + w) * 64 + l;
+                if (i < I) {
+#pragma unroll
+                    for (int s = 0; s < RT; ++s) {
+                        if (s < R) {
+                            const TC v = (TC)xc[q][s];
+                            A[i * R + s] = v;
+                            sF[i * RT + s] = (double)v;   // the stored (rounded) factor, for its Gram
+                        }
+                    }
+                }
+            }
+        }
+        if (tid == 0) *sFlag = ok ? 1 : 0;
+    }
+    __syncthreads();
+    return *sFlag != 0;
+}
+
+// Gram of the stored factor (rows of stride 16 in sF) on the float64 matrix
+// core, wave 0: D += F_b^T F_b over blocks F_b of four rows (rows past I read
+// as zero); lane l supplies F(i0 + l / 16, l mod 16) as both operands.
+__device__ __forceinline__ void wave_gram16(const double* sF, int64_t I, int R, double* gout) {
+    const int l = threadIdx.x & 63;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t i0 = 0; i0 < I; i0 += 4) {
+        const int64_t i = i0 + (l >> 4);
+        const double v = i < I ? sF[i * 16 + (l & 15)] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v, v, acc, 0, 0, 0);
+    }
+    // output of the float64 16x16x4 product: lane l, item j holds D[(l >> 4) + 4 j][l & 15]
+    const int c = l & 15;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int r = (l >> 4) + 4 * j;
+        if (r < R && c < R) gout[r * R + c] = acc[j];
+    }
+}
+
+// eq. 2.14 for mode n (0-based): A^(n) <- G Gamma^{-1}, Gamma symmetric positive
+// definite.  Gauss-Jordan elimination without pivoting on the augmented
+// system [Gamma | G^T] (float64): step k scales row k by 1/Gamma'_kk and
+// removes column k from every other row, so after R steps the right part is
+// Gamma^{-1} G^T = (A^(n))^T.  The pivots are those of Gamma = L D L^T, all
+// positive for an SPD matrix; a pivot that is not positive and finite ends
+// the attempt (the caller retries once with `jitter`: Gamma + 1e-12
+// tr(Gamma)/R I, G formed again).  Every thread keeps its entries of the
+// system in registers (G^T entries (s, i) with s = tid mod RT, so one
+// multiplier per step); a step needs only the pivot row and column, which
+// their owners publish to LDS (two alternating copies, one barrier per step).
+// Then the factor is stored (rounded to TC) and the Gram of the stored values
+// formed.  G in sG is only read, so a retry and the cost can use it again.
+// Returns false, leaving A^(n) and grams[n] untouched, if Gamma is not
+// positive definite.
+template <typename TC, int RT>
+__device__ __forceinline__ bool block_solve(const EpiArgs<TC>& a, int n, double* sG, double* sGam, double* sPub,
+                                            double* spart, int* sFlag, bool jitter) {
+    static_assert(kEpiThreads % RT == 0, "a thread's entries of G^T share one row of the system");
+    constexpr int kPerX = kEpiGCap / kEpiThreads;                      // G^T entries per thread
+    constexpr int kPerG = (RT * RT + kEpiThreads - 1) / kEpiThreads;   // Gamma entries per thread
+    const int tid = threadIdx.x;
+    const int R = a.fs.R;
+    const int64_t I = a.fs.dims[n];
+    const int nx = (int)(I * RT);          // <= kEpiGCap
+    const int srow = tid & (RT - 1);
+    // publication copies c = 0, 1: pivot row of Gamma' (RT), its pivot column (RT), pivot row of G^T (I)
+    const int pub = 2 * RT + (int)I;
+    auto prow = [&](int c) { return sPub + c * pub; };
+    auto pcol = [&](int c) { return sPub + c * pub + RT; };
+    auto px = [&](int c) { return sPub + c * pub + 2 * RT; };
+
+    block_gamma<TC, RT>(a, n, sGam);
+    __syncthreads();
+    CPG_EPI_MARK(20);
+    if (jitter) {
+        double tr = 0.0;
+        for (int c = 0; c < R; ++c) tr += sGam[c * RT + c];
+        __syncthreads();
+        if (tid < R) sGam[tid * RT + tid] += 1e-12 * tr / R;
+        __syncthreads();
+    }
+    if constexpr (RT <= 16) {
+        if (!wave_eliminate<TC, RT>(a, n, sG, sGam, sPub, sFlag)) return false;
+        CPG_EPI_MARK(22);
+        if constexpr (RT == 16) {
+            if (tid < 64) wave_gram16(sPub, I, R, a.grams + (int64_t)n * R * R);
+            __syncthreads();
+        } else {
+            block_gram_rows<RT>(sPub, I, R, a.grams + (int64_t)n * R * R, spart);
+        }
+        CPG_EPI_MARK(23);
+        return true;
+    }
+    double g[kPerG], x[kPerX];
+#pragma unroll
+    for (int v = 0; v < kPerG; ++v) {
+        const int e = tid + v * kEpiThreads;
+        const int r = e / RT, j = e & (RT - 1);
+        g[v] = (e < RT * RT && r < R && j < R) ? sGam[r * RT + j] : 0.0;
+        if (e < RT * RT && r == 0) prow(0)[j] = g[v];
+        if (e < RT * RT && j == 0) pcol(0)[r] = g[v];
+    }
+#pragma unroll
+    for (int u = 0; u < kPerX; ++u) {
+        const int e = tid + u * kEpiThreads;
+        x[u] = (e < nx && srow < R) ? sG[e] : 0.0;
+        if (e < nx && srow == 0) px(0)[e / RT] = x[u];
+    }
+    __syncthreads();
+    for (int k = 0; k < R; ++k) {
+        const int c = k & 1;
+        // every read of the step first (entries past the system read nothing), then the pivot test
+        const double piv = prow(c)[k];   // the same value in every thread
+        const double m = pcol(c)[srow];
+        double rk[kPerG], cr[kPerG], xk[kPerX];
+#pragma unroll
+        for (int v = 0; v < kPerG; ++v) {
+            rk[v] = cr[v] = 0.0;
+            if (v * kEpiThreads < RT * RT) {   // uniform over the block
+                const int e = min(tid + v * kEpiThreads, RT * RT - 1);
+                rk[v] = prow(c)[e & (RT - 1)];
+                cr[v] = pcol(c)[e / RT];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kPerX; ++u) {
+            xk[u] = 0.0;
+            if (u * kEpiThreads < nx) xk[u] = px(c)[min(tid + u * kEpiThreads, nx - 1) / RT];
+        }
+        if (!(piv > 0.0) || !isfinite(piv)) return false;
+        const double rp = rcp_d(piv);
+        const int cn = c ^ 1;
+#pragma unroll
+        for (int v = 0; v < kPerG; ++v) {
+            if (v * kEpiThreads >= RT * RT) break;
+            const int e = tid + v * kEpiThreads;
+            const int r = e / RT, j = e & (RT - 1);
+            const double t = rk[v] * rp;
+            if (j > k) g[v] = r == k ? t : g[v] - cr[v] * t;   // columns <= k are not read again
+            if (e < RT * RT && r == k + 1) prow(cn)[j] = g[v];
+            if (e < RT * RT && j == k + 1) pcol(cn)[r] = g[v];
+        }
+#pragma unroll
+        for (int u = 0; u < kPerX; ++u) {
+            if (u * kEpiThreads >= nx) break;
+            const int e = tid + u * kEpiThreads;
+            const double t = xk[u] * rp;
+            x[u] = srow == k ? t : x[u] - m * t;
+            if (e < nx && srow == k + 1) px(cn)[e / RT] = x[u];
+        }
+        __syncthreads();
+    }
+    CPG_EPI_MARK(21);
+    // the publication copies are no longer read (barrier above): the stored
+    // (rounded) factor goes there, rows i of stride RT, for its Gram
+    TC* A = (TC*)a.fs.A[n];
+#pragma unroll
+    for (int u = 0; u < kPerX; ++u) {
+        const int e = tid + u * kEpiThreads;
+        if (e < nx && srow < R) {
+            const TC v = (TC)x[u];
+            A[(int64_t)(e / RT) * R + srow] = v;
+            sPub[e] = (double)v;
+        }
+    }
+    __syncthreads();
+    CPG_EPI_MARK(22);
+    block_gram_rows<RT>(sPub, I, R, a.grams + (int64_t)n * R * R, spart);
+    CPG_EPI_MARK(23);
     return true;
 }
 
-// eq. 2.14 for mode n (0-based) with G^(n) in sG: A^(n) <- G Gamma^{-1}.
-// Gamma by the block; W = L^{-1} by one wave (one jittered retry with
-// Gamma + 1e-12 tr(Gamma)/R I); Gamma^{-1} = W^T W and A^(n) = G Gamma^{-1}
-// by the block, then the Gram of the new factor: five block barriers per
-// mode.  Returns false (leaving A^(n) and grams[n] untouched) if Gamma is not
-// positive definite.
 template <typename TC, int RT>
-__device__ __forceinline__ bool block_solve(const EpiArgs<TC>& a, int n, const double* sG, double* sGam, double* sL,
-                                            double* sA, double* spart, int* sOk) {
-    if constexpr (RT > 16) {
-        return block_solve_lds<TC, RT>(a, n, sG, sGam, sL, sA, spart, sOk);
-    } else {
-        static_assert(2 * RT * RT <= kEpiThreads, "two threads per Gram entry");
-        static_assert(RT * RT + RT <= kEpiThreads, "Cholesky scratch fits the partial-sum buffer");
-        const int tid = threadIdx.x;
-        const int R = a.fs.R;
-        const int64_t I = a.fs.dims[n];
-        block_gamma<TC, RT>(a, n, sGam);
-        __syncthreads();
-        CPG_EPI_MARK(20);
-        if (tid < 64) {
-            bool good = wave_chol_inverse<RT>(sGam, R, 0.0, spart, sL);
-            if (!good) {
-                double tr = 0.0;
-                for (int c = 0; c < R; ++c) tr += sGam[c * RT + c];
-                good = wave_chol_inverse<RT>(sGam, R, 1e-12 * tr / R, spart, sL);
-            }
-            if (tid == 0) *sOk = good ? 1 : 0;
-        }
-        __syncthreads();
-        CPG_EPI_MARK(21);
-        if (!*sOk) return false;
-        // Gamma^{-1} = W^T W into sGam (W: lower triangular, zero above the
-        // diagonal and in the padding, so the sums run over the whole tile)
-        for (int e = tid; e < R * R; e += kEpiThreads) {
-            const int r = e / R, c = e - (e / R) * R;
-            double acc[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int i = 0; i < RT; ++i) acc[i & 3] += sL[i * RT + r] * sL[i * RT + c];
-            sGam[r * RT + c] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
-        }
-        __syncthreads();
-        // A^(n) = G Gamma^{-1}
-        TC* A = (TC*)a.fs.A[n];
-        for (int64_t o = tid; o < I * R; o += kEpiThreads) {
-            const int64_t i = o / R;
-            const int c = (int)(o - i * R);
-            double acc[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int s = 0; s < RT; ++s)
-                if (s < R) acc[s & 3] += sG[i * RT + s] * sGam[s * RT + c];
-            const TC v = (TC)((acc[0] + acc[1]) + (acc[2] + acc[3]));
-            A[o] = v;
-            sA[o] = (double)v;   // the stored (rounded) factor, for its Gram
-        }
-        __syncthreads();
-        CPG_EPI_MARK(22);
-        CPG_EPI_MARK(23);
-        // Gram of the new factor: entry (r, c) over two threads, rows split by parity
-        {
-            const int E = R * R;
-            double acc[4] = {0.0, 0.0, 0.0, 0.0};
-            if (tid < 2 * E) {
-                const int e = tid % E, h = tid / E;
-                const int r = e / R, c = e - (e / R) * R;
-                int64_t i = h;
-                for (; i + 6 < I; i += 8) {
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) acc[u] += sA[(i + 2 * u) * R + r] * sA[(i + 2 * u) * R + c];
-                }
-                for (; i < I; i += 2) acc[0] += sA[i * R + r] * sA[i * R + c];
-            }
-            spart[tid] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
-            __syncthreads();
-            if (tid < E) a.grams[(int64_t)n * E + tid] = spart[tid] + spart[tid + E];
-            __syncthreads();
-        }
-        return true;
-    }
-}
-
-template <typename TC, int RT>
-__device__ __forceinline__ void epilogue_body(const EpiArgs<TC>& a, double* sG, double* sGam, double* sW,
-                                              double* spart, double* sKR, d4* spart4, int* sOkp) {
-    int& sOk = *sOkp;
+__device__ __forceinline__ void epilogue_body(const EpiArgs<TC>& a, double* sG, double* sGam,
+                                              double* spart, double* sKR, d4* spart4, int* sFlag) {
     const int tid = threadIdx.x;
     CPG_EPI_MARK(0);
     const int R = a.fs.R;
@@ -650,9 +664,13 @@ __device__ __forceinline__ void epilogue_body(const EpiArgs<TC>& a, double* sG, 
         }
         CPG_EPI_MARK(3 + 3 * step);
         if (a.update) {
-            if (!block_solve<TC, RT>(a, n - 1, sG, sGam, sW, sKR, spart, &sOk)) {
-                if (tid == 0) atomicOr(a.flags, 1);
+            // one jittered retry if Gamma is not positive definite
+            bool solved = false;
+            for (int attempt = 0; attempt < 2 && !solved; ++attempt) {
+                if (attempt > 0) __syncthreads();
+                solved = block_solve<TC, RT>(a, n - 1, sG, sGam, sKR, spart, sFlag, attempt == 1);
             }
+            if (!solved && tid == 0) atomicOr(a.flags, 1);
         } else if (!(step == 0 && a.Gpre == a.Gout[n - 1])) {
             TC* G = a.Gout[n - 1];
             for (int64_t o = tid; o < I * R; o += kEpiThreads) {
@@ -701,16 +719,15 @@ template <typename TC, int RT>
 __global__ __launch_bounds__(kEpiThreads) void k_epilogue(EpiArgs<TC> a0, EpiArgs<TC> a1) {
     __shared__ double sG[kEpiGCap];
     __shared__ double sGam[RT * RT];
-    __shared__ double sW[RT * (RT + 1)];
     __shared__ double spart[kEpiThreads];
     __shared__ double sKR[kEpiKRCap];
     __shared__ d4 spart4[kEpiThreads];
-    __shared__ int sOk;
+    __shared__ int sFlag;
     // two inlined copies so that each reads its own kernel argument directly
     if (blockIdx.x == 0)
-        epilogue_body<TC, RT>(a0, sG, sGam, sW, spart, sKR, spart4, &sOk);
+        epilogue_body<TC, RT>(a0, sG, sGam, spart, sKR, spart4, &sFlag);
     else
-        epilogue_body<TC, RT>(a1, sG, sGam, sW, spart, sKR, spart4, &sOk);
+        epilogue_body<TC, RT>(a1, sG, sGam, spart, sKR, spart4, &sFlag);
 }
 
 template <typename TC>
