@@ -34,8 +34,8 @@
  *   F32      F32           BF16_REFINED    + residual terms (hi*lo + lo*hi) in the same pass
  *   BF16     F32           BF16            Y stored bf16, Khatri-Rao tiles bf16
  *   BF16     F32           BF16_REFINED    + Y*KR_lo term (Y is exact in bf16)
- *   Gram matrices, the Cholesky solve of eq. 2.14, ||Y||^2 and the cost of
- *   eq. 2.12 are float64 in every mode.
+ *   Gram matrices, the normal-equation solve of eq. 2.14, ||Y||^2 and the
+ *   cost of eq. 2.12 are float64 in every mode.
  *
  * Status codes: every call returns a cpg_status (0 = success, < 0 = error).
  * On error no caller buffer is freed; outputs are unspecified unless stated.

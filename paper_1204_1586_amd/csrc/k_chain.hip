@@ -2,7 +2,7 @@
 //  * fixed-order float64 reduction of the split partial contractions;
 //  * the peel-off chain steps of eqs. 3.20 / 3.22 (one mode product);
 //  * the per-mode gradient of cp_gradient 'right' / 'left' (eqs. 3.12, 3.16);
-//  * float64 Gram matrices, the Cholesky solve of eq. 2.14, ||Y||^2, and the
+//  * float64 Gram matrices, the Cholesky solve of eq. 2.14 (generic path), ||Y||^2, and the
 //    cost of eq. 2.12 with fit = 1 - ||Y - Yhat|| / ||Y||.
 // All reductions run in a fixed order, so results are bitwise reproducible.
 #include "cpg_device.h"

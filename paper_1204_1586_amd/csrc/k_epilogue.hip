@@ -5,9 +5,9 @@
 //     'left', eq. 3.16) in float64 in LDS,
 //   * either writes it out (all-mode gradient) or applies the ALS update of
 //     eq. 2.14 with the Section 4 order: Gamma = Hadamard product of the other
-//     modes' float64 Grams, Cholesky (one wave, rows in registers, one
-//     jittered retry), W = L^{-1}, Gamma^{-1} = W^T W, A^(n) = G Gamma^{-1},
-//     then the Gram of the new factor,
+//     modes' float64 Grams, A^(n) = G Gamma^{-1} by Gauss-Jordan elimination
+//     of [Gamma | G^T] in registers (one jittered retry), then the Gram of the
+//     new factor,
 //   * steps the chain with the (updated) factor: eq. 3.20 on the right,
 //     eq. 3.22 on the left.
 // The left epilogue of an ALS sweep ends with the cost of eq. 2.12 and the
