@@ -76,6 +76,7 @@ hipError_t launch_reduce_parts(int fdt, const void* parts, int64_t nparts, int64
 // Grams when `grams` is set.
 // ---------------------------------------------------------------------------
 constexpr int kRfBatch = 16;   // partial loads in flight per thread
+constexpr int kRfThreads = 512;  // one term per thread at 64 terms x 4 float4 x 2 rows
 
 __device__ __forceinline__ void reduce_first_rows(const ReduceFirst& a, int64_t blk, const KrGen& kg, d4s* spart) {
     const int R = kg.R;
@@ -88,7 +89,7 @@ __device__ __forceinline__ void reduce_first_rows(const ReduceFirst& a, int64_t 
     const int q = tid & (nqp - 1);
     const int sub = (tid / nqp) & (rpb - 1);  // output row of the block this thread serves
     const int tslot = tid / (nqp * rpb);
-    const int tstep = 256 / (nqp * rpb);
+    const int tstep = kRfThreads / (nqp * rpb);
     const int64_t i = blk * rpb + sub;
     const int64_t rstride = a.side == 0 ? 1 : a.I;            // row of term t: rbase + t * rstride
     const int64_t rbase = a.side == 0 ? a.T * i : i;
@@ -151,7 +152,7 @@ __device__ __forceinline__ void reduce_first_rows(const ReduceFirst& a, int64_t 
     // sum over the term slots (fixed tree order); slot 0 of (sub, q) ends in spart[sub * nqp + q]
     spart[tid] = g;
     __syncthreads();
-    for (int st = 128; st >= nqp * rpb; st >>= 1) {
+    for (int st = kRfThreads / 2; st >= nqp * rpb; st >>= 1) {
         if (tid < st) {
             spart[tid].x += spart[tid + st].x;
             spart[tid].y += spart[tid + st].y;
@@ -181,8 +182,8 @@ struct RfSides {
     int n;
 };
 
-__global__ __launch_bounds__(256) void k_reduce_first(RfSides sd, KrGen kg, double* __restrict__ grams) {
-    __shared__ d4s spart[256];
+__global__ __launch_bounds__(kRfThreads) void k_reduce_first(RfSides sd, KrGen kg, double* __restrict__ grams) {
+    __shared__ d4s spart[kRfThreads];
     const int64_t b = blockIdx.x;
     if (b < sd.first[sd.n]) {
         int k = 0;
@@ -197,12 +198,12 @@ __global__ __launch_bounds__(256) void k_reduce_first(RfSides sd, KrGen kg, doub
         const int tid = threadIdx.x;
         const float* A = kg.A[m];
         const int64_t I = kg.fd[m].d;
-        constexpr int kChunk = 2048;                 // floats: the 256 float4 of spart
-        constexpr int kPer = kChunk / 256;
+        constexpr int kChunk = 4 * kRfThreads;       // floats: the float4 of spart
+        constexpr int kPer = kChunk / kRfThreads;
         constexpr int kGrp = 4;                      // Gram entries per thread and pass
         float* sA = reinterpret_cast<float*>(spart);
         const int64_t rows_per = kChunk / R;
-        for (int e0 = 0; e0 < R * R; e0 += 256 * kGrp) {
+        for (int e0 = 0; e0 < R * R; e0 += kRfThreads * kGrp) {
             double acc[kGrp];
 #pragma unroll
             for (int k = 0; k < kGrp; ++k) acc[k] = 0.0;
@@ -210,16 +211,16 @@ __global__ __launch_bounds__(256) void k_reduce_first(RfSides sd, KrGen kg, doub
                 const int nf = (int)(min(rows_per, I - i0) * R);
                 float v[kPer];
 #pragma unroll
-                for (int u = 0; u < kPer; ++u) v[u] = A[i0 * R + min(tid + 256 * u, nf - 1)];
+                for (int u = 0; u < kPer; ++u) v[u] = A[i0 * R + min(tid + kRfThreads * u, nf - 1)];
                 __syncthreads();   // the previous chunk is consumed
 #pragma unroll
                 for (int u = 0; u < kPer; ++u)
-                    if (tid + 256 * u < nf) sA[tid + 256 * u] = v[u];
+                    if (tid + kRfThreads * u < nf) sA[tid + kRfThreads * u] = v[u];
                 __syncthreads();
                 const int nr = nf / R;
 #pragma unroll
                 for (int k = 0; k < kGrp; ++k) {
-                    const int e = e0 + tid + 256 * k;
+                    const int e = e0 + tid + kRfThreads * k;
                     if (e < R * R) {
                         const int r = e / R, c = e - (e / R) * R;
                         int ii = 0;
@@ -239,7 +240,7 @@ __global__ __launch_bounds__(256) void k_reduce_first(RfSides sd, KrGen kg, doub
             }
 #pragma unroll
             for (int k = 0; k < kGrp; ++k) {
-                const int e = e0 + tid + 256 * k;
+                const int e = e0 + tid + kRfThreads * k;
                 if (e < R * R) grams[(int64_t)m * R * R + e] = acc[k];
             }
         }
@@ -264,7 +265,7 @@ hipError_t launch_reduce_first(const ReduceFirst* sides, int nsides, const KrGen
     sd.first[nsides] = nb;
     const int64_t total = nb + (grams ? kg.N : 0);
     if (total == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reduce_first, dim3((unsigned)total), dim3(256), 0, s, sd, kg, grams);
+    hipLaunchKernelGGL(k_reduce_first, dim3((unsigned)total), dim3(kRfThreads), 0, s, sd, kg, grams);
     return hipGetLastError();
 }
 
