@@ -149,20 +149,26 @@ __device__ __forceinline__ void reduce_first_rows(const ReduceFirst& a, int64_t 
             g.w += (double)z.w * w[3];
         }
     }
-    // sum over the term slots (fixed tree order); slot 0 of (sub, q) ends in spart[sub * nqp + q]
-    spart[tid] = g;
-    __syncthreads();
-    for (int st = kRfThreads / 2; st >= nqp * rpb; st >>= 1) {
-        if (tid < st) {
-            spart[tid].x += spart[tid + st].x;
-            spart[tid].y += spart[tid + st].y;
-            spart[tid].z += spart[tid + st].z;
-            spart[tid].w += spart[tid + st].w;
-        }
-        __syncthreads();
+    // sum over the term slots in a fixed order: a butterfly over the slots of
+    // each wave, then the waves' sums in wave order
+    const int grp = nqp * rpb;   // threads of one term slot (a power of two <= 64)
+    for (int off = grp; off < 64; off <<= 1) {
+        g.x += __shfl_xor(g.x, off);
+        g.y += __shfl_xor(g.y, off);
+        g.z += __shfl_xor(g.z, off);
+        g.w += __shfl_xor(g.w, off);
     }
-    if (tid < nqp * rpb && q < nq && i < a.I) {
-        const d4s v = spart[tid];
+    if ((tid & 63) < grp) spart[(tid >> 6) * grp + (tid & 63)] = g;
+    __syncthreads();
+    if (tid < grp && q < nq && i < a.I) {
+        d4s v = spart[tid];
+        for (int wv = 1; wv < kRfThreads / 64; ++wv) {
+            const d4s u = spart[wv * grp + tid];
+            v.x += u.x;
+            v.y += u.y;
+            v.z += u.z;
+            v.w += u.w;
+        }
         const double vv[4] = {v.x, v.y, v.z, v.w};
         float* out = a.G + i * a.out_ld + 4 * q;
 #pragma unroll

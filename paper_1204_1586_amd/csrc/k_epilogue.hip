@@ -490,8 +490,9 @@ __device__ __forceinline__ void wave_gram16(const double* sF, int64_t I, int R, 
 // removes column k from every other row, so after R steps the right part is
 // Gamma^{-1} G^T = (A^(n))^T.  The pivots are those of Gamma = L D L^T, all
 // positive for an SPD matrix; a pivot that is not positive and finite ends
-// the attempt (the caller retries once with `jitter`: Gamma + 1e-12
-// tr(Gamma)/R I, G formed again).  Every thread keeps its entries of the
+// the attempt (the caller retries once with `jitter`: Gamma formed again and
+// shifted by 1e-12 tr(Gamma)/R I).  Without `jitter`, sGam already holds Gamma
+// (the caller forms it while the chain step's loads are in flight).  Every thread keeps its entries of the
 // system in registers (G^T entries (s, i) with s = tid mod RT, so one
 // multiplier per step); a step needs only the pivot row and column, which
 // their owners publish to LDS (two alternating copies, one barrier per step).
@@ -516,10 +517,11 @@ __device__ __forceinline__ bool block_solve(const EpiArgs<TC>& a, int n, double*
     auto pcol = [&](int c) { return sPub + c * pub + RT; };
     auto px = [&](int c) { return sPub + c * pub + 2 * RT; };
 
-    block_gamma<TC, RT>(a, n, sGam);
-    __syncthreads();
-    CPG_EPI_MARK(20);
     if (jitter) {
+        // the retry: Gamma formed again, then the diagonal shifted
+        __syncthreads();
+        block_gamma<TC, RT>(a, n, sGam);
+        __syncthreads();
         double tr = 0.0;
         for (int c = 0; c < R; ++c) tr += sGam[c * RT + c];
         __syncthreads();
@@ -636,6 +638,9 @@ __device__ __forceinline__ void epilogue_body(const EpiArgs<TC>& a, double* sG, 
     for (int step = 0; step < a.n_count; ++step) {
         const int n = (a.side == 0) ? a.n_first - step : a.n_first + step;   // paper's mode
         const int64_t I = a.fs.dims[n - 1];
+        // Gamma of this mode's update (the Grams it reads are final by now); its
+        // loads go out together with the chain step's
+        if (a.update) block_gamma<TC, RT>(a, n - 1, sGam);
         if (step > 0) {
             if (a.side == 0) {
                 // vec R^(r,n) = reshape(R^(r,n+1), [J_n, I_{n+1}]) a_r^(n+1)   (eq. 3.20)
