@@ -56,6 +56,30 @@ constexpr int kEpiKRCap = 4096;    // largest (terms x ld) of Khatri-Rao rows / 
 // Launch `nsides` (1 or 2) epilogue blocks; args[b] drives block b.
 hipError_t launch_epilogue(int fdt, int R, const void* args, int nsides, hipStream_t stream);
 
+// ALS update of a side with exactly two modes on many blocks (float32
+// factors, R <= 16): the side's first mode n1 from its precomputed gradient,
+// then the last mode n2, whose gradient is the chain step of the first
+// (eq. 3.20: right, n2 = 1; eq. 3.22: left, n2 = N) and whose rows are
+// independent: block b forms and solves rows [b rows, (b + 1) rows).
+struct EpiRows {
+    FacSet<float> fs;
+    int side;              // 0 = right (n2 = n1 - 1 = 1), 1 = left (n2 = n1 + 1 = N)
+    int n1, n2;            // paper's 1-based modes
+    const float* Z;        // P_R (rows i_1 + I_1 i_2) or P_L (rows i_{N-1} + I_{N-1} i_N), stride ld
+    int ld;
+    const float* Gpre;     // G^(n1), I_n1 x R
+    int rows;              // rows of A^(n2) per block
+    int cost;              // last pass of a sweep: cost of eq. 2.12 and fit
+    double* grams;         // [N][R][R], read; grams[n1], grams[n2] written
+    double* scal;          // as in EpiArgs
+    int* flags;            // bit 0: not SPD, bit 1: non-finite cost
+    int* ticket;           // zero between launches; the last block to finish resets it
+    double* part;          // one float64 per block (cost partials)
+};
+constexpr int kEpiRowsMaxBlocks = 16;
+constexpr int kEpiRowsCells = 512;   // rows x rank tile of one block's slice
+hipError_t launch_epi_rows(const EpiRows& a, hipStream_t stream);
+
 // Tiling of one contraction pass over the J x K view Y_(1:n*).
 struct Tiling {
     int kernel;        // 1 = generic vector ALU, 2 = float32 MFMA, 3 = bf16 MFMA
@@ -132,8 +156,9 @@ inline __host__ __device__ int rf_rows_per_block(int side, int ld) {
         while (2 * r * ld * 4 <= 128) r *= 2;
     return r;
 }
+// `clear_flags`, if set: flags[0..7] are zeroed by the kernel (the start of an ALS sweep).
 hipError_t launch_reduce_first(const ReduceFirst* sides, int nsides, const KrGen& kg, double* grams,
-                               hipStream_t stream);
+                               hipStream_t stream, int* clear_flags = nullptr);
 
 // out[row][r] = sum_p parts[p][row][r] over rows x ld entries (float64, fixed order)
 hipError_t launch_reduce_parts(int fdt, const void* parts, int64_t nparts, int64_t rows, int ld,

@@ -42,7 +42,8 @@ struct cpgrad_plan_s {
     double* grams = nullptr;
     double* scal = nullptr;   // [0]=||Y||^2 [2]=cost [3]=fit [4]=inner [5]=||Yhat||^2 [6]=inner(cp_fit)
     double* red = nullptr;    // reduction scratch (1024 doubles)
-    int* flags = nullptr;
+    int* flags = nullptr;     // [0] status bits, [8] ticket of the many-block ALS epilogue
+    double* rpart = nullptr;  // per-block cost partials of the many-block ALS epilogue
     double* host = nullptr;   // pinned readback: scal[0..7], flags
     const void* bound = nullptr;
     // learned extrapolation step: start / previous-update / extrapolated factors, features, sigma
@@ -182,6 +183,7 @@ static int configure(cpgrad_plan_s* p) {
     const size_t oS = off;      off += al(16 * 8);
     const size_t oRed = off;    off += al(kRedScratch * 8);
     const size_t oF = off;      off += al(16 * sizeof(int));
+    const size_t oRp = off;     off += al(kEpiRowsMaxBlocks * 8);
     if (off > p->ws_bytes) {
         release(p);
         void* mem = nullptr;
@@ -206,6 +208,7 @@ static int configure(cpgrad_plan_s* p) {
     p->scal = (double*)(b + oS);
     p->red = (double*)(b + oRed);
     p->flags = (int*)(b + oF);
+    p->rpart = (double*)(b + oRp);
 
     if (hipMemsetAsync(p->scal, 0, 16 * 8, p->stream) != hipSuccess) return CPG_ERR_HIP;
     if (hipMemsetAsync(p->flags, 0, 16 * sizeof(int), p->stream) != hipSuccess) return CPG_ERR_HIP;
@@ -308,7 +311,8 @@ static hipError_t run_contract(cpgrad_plan_s* p, const void* Y, const AnyFacSet&
 // from, and P_R / P_L are not stored, since nothing reads them afterwards.
 // Returns CPG_OK; *fused tells whether the gradients were formed.
 static int finish_partials(cpgrad_plan_s* p, const FacSet<float>* fs, const Tiling& t, int roles, void* Gr = nullptr,
-                           void* Gl = nullptr, bool grams = false, bool* fused = nullptr, void* const* Gall = nullptr) {
+                           void* Gl = nullptr, bool grams = false, bool* fused = nullptr, void* const* Gall = nullptr,
+                           int* clear_flags = nullptr) {
     const bool fr = p->fused_first && fs && (roles & 1) && Gr;
     const bool fl = p->fused_first && fs && (roles & 2) && Gl;
     if (fused) *fused = fr || fl;
@@ -337,7 +341,7 @@ static int finish_partials(cpgrad_plan_s* p, const FacSet<float>* fs, const Tili
             sd[n++] = ReduceFirst{(const float*)p->PLpart, t.n_jr, p->K, ld, 0, p->Kn[ns + 1], p->dims[ns],
                                   ns, 1, nullptr, last ? (float*)Gall[N - 1] : (float*)p->chain[2], last ? R : ld};
         }
-        CPG_TRY(launch_reduce_first(sd, n, kr_gen(p, *fs), grams ? p->grams : nullptr, p->stream));
+        CPG_TRY(launch_reduce_first(sd, n, kr_gen(p, *fs), grams ? p->grams : nullptr, p->stream, clear_flags));
     }
     if ((roles & 1) && !fr) CPG_TRY(launch_reduce_parts(p->fdt, p->PRpart, t.n_kc, p->J, p->ld, p->PR, p->stream));
     if ((roles & 2) && !fl) CPG_TRY(launch_reduce_parts(p->fdt, p->PLpart, t.n_jr, p->K, p->ld, p->PL, p->stream));
@@ -641,6 +645,39 @@ __global__ void k_zero_flags(int* f) {
 
 // One ALS sweep enqueued on the plan's stream (no host wait): cost and fit end
 // in scal[2], scal[3], failures in flags.
+// A side of the ALS sweep with exactly two modes goes through the many-block
+// epilogue (float32 factors, R <= 16, first gradient precomputed): rows of
+// the side's last mode per block, at most kEpiRowsMaxBlocks blocks.
+static int rows_per_block(int64_t I) { return (int)((I + kEpiRowsMaxBlocks - 1) / kEpiRowsMaxBlocks); }
+
+static bool rows_side_ok(const cpgrad_plan_s* p, int side) {
+    if (p->fdt != CPG_F32 || p->R > 16 || !p->fused_first) return false;
+    if ((side == 0 ? p->nstar : p->N - p->nstar) != 2) return false;
+    const int64_t rt = p->R <= 4 ? 4 : 16;
+    const int64_t I1 = p->dims[side == 0 ? p->nstar - 1 : p->nstar], I2 = p->dims[side == 0 ? 0 : p->N - 1];
+    return I1 * rt <= kEpiGCap && I2 * rt <= kEpiGCap && rows_per_block(I2) * rt <= kEpiRowsCells;
+}
+
+static int run_rows(cpgrad_plan_s* p, const FacSet<float>& fs, int side, bool cost) {
+    EpiRows e{};
+    e.fs = fs;
+    e.side = side;
+    e.n1 = side == 0 ? p->nstar : p->nstar + 1;
+    e.n2 = side == 0 ? 1 : p->N;
+    e.Z = (const float*)(side == 0 ? p->PR : p->PL);
+    e.ld = p->ld;
+    e.Gpre = (const float*)p->Gtmp;
+    e.rows = rows_per_block(p->dims[e.n2 - 1]);
+    e.cost = cost ? 1 : 0;
+    e.grams = p->grams;
+    e.scal = p->scal;
+    e.flags = p->flags;
+    e.ticket = p->flags + 8;
+    e.part = p->rpart;
+    CPG_TRY(launch_epi_rows(e, p->stream));
+    return CPG_OK;
+}
+
 static int als_sweep_core(cpgrad_plan_s* p, const void* Y, void* const* A) {
     const AnyFacSet fs = facsets(p, (const void* const*)A);
     const bool epi = epilogue_fits(p);
@@ -653,9 +690,11 @@ static int als_sweep_core(cpgrad_plan_s* p, const void* Y, void* const* A) {
     CPG_TRY(run_contract(p, Y, fs, p->t_right, 1));
     const FacSet<float>* fsf = p->fdt == CPG_F32 ? &fs.f : nullptr;
     bool pre = false;
-    int st = finish_partials(p, fsf, p->t_right, 1, p->Gtmp, nullptr, true, &pre);
+    int st = finish_partials(p, fsf, p->t_right, 1, p->Gtmp, nullptr, true, &pre, nullptr, p->flags);
     if (st) return st;
-    if (epi)
+    if (epi && pre && rows_side_ok(p, 0))
+        st = run_rows(p, fs.f, 0, false);
+    else if (epi)
         st = p->fdt == CPG_F64 ? run_side<double>(p, fs.d, 0, A, nullptr, true, true, false)
                                : run_side<float>(p, fs.f, 0, A, nullptr, true, true, false,
                                                  pre ? (const float*)p->Gtmp : nullptr, pre);
@@ -666,7 +705,10 @@ static int als_sweep_core(cpgrad_plan_s* p, const void* Y, void* const* A) {
     CPG_TRY(run_contract(p, Y, fs, p->t_left, 2));
     st = finish_partials(p, fsf, p->t_left, 2, nullptr, p->Gtmp, false, &pre);
     if (st) return st;
-    if (epi) {
+    if (epi && pre && rows_side_ok(p, 1)) {
+        st = run_rows(p, fs.f, 1, true);
+        if (st) return st;
+    } else if (epi) {
         st = p->fdt == CPG_F64 ? run_side<double>(p, fs.d, 1, A, nullptr, true, false, true)
                                : run_side<float>(p, fs.f, 1, A, nullptr, true, false, true,
                                                  pre ? (const float*)p->Gtmp : nullptr);

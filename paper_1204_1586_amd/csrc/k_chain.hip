@@ -186,11 +186,13 @@ struct RfSides {
     ReduceFirst s[kMaxReduceSides];
     int64_t first[kMaxReduceSides + 1];   // first block of each side; first[n]: blocks of all sides
     int n;
+    int* clear_flags;                     // zeroed by block 0 when set
 };
 
 __global__ __launch_bounds__(kRfThreads) void k_reduce_first(RfSides sd, KrGen kg, double* __restrict__ grams) {
     __shared__ d4s spart[kRfThreads];
     const int64_t b = blockIdx.x;
+    if (b == 0 && sd.clear_flags && threadIdx.x < 8) sd.clear_flags[threadIdx.x] = 0;
     if (b < sd.first[sd.n]) {
         int k = 0;
         while (k + 1 < sd.n && b >= sd.first[k + 1]) ++k;
@@ -254,10 +256,11 @@ __global__ __launch_bounds__(kRfThreads) void k_reduce_first(RfSides sd, KrGen k
 }
 
 hipError_t launch_reduce_first(const ReduceFirst* sides, int nsides, const KrGen& kg, double* grams,
-                               hipStream_t s) {
+                               hipStream_t s, int* clear_flags) {
     if (nsides < 1 || nsides > kMaxReduceSides) return hipErrorInvalidValue;
     RfSides sd{};
     sd.n = nsides;
+    sd.clear_flags = clear_flags;
     int64_t nb = 0;
     for (int k = 0; k < nsides; ++k) {
         const ReduceFirst& a = sides[k];

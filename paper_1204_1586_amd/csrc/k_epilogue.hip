@@ -317,21 +317,26 @@ __device__ __forceinline__ void block_grams_all(const FacSet<TC>& fs, double* gr
 }
 
 // Gamma (R x R, stride RT) = Hadamard product of the float64 Grams of every
-// mode but n (eq. 2.14).
-template <typename TC, int RT>
-__device__ __forceinline__ void block_gamma(const EpiArgs<TC>& a, int n, double* sGam) {
-    const int R = a.fs.R;
-    const int N = a.fs.N;
+// mode but n (eq. 2.14); mode `ovr_mode`'s Gram, if any, is read from `ovr`
+// (R x R) instead of `grams`.
+template <int RT>
+__device__ __forceinline__ void gamma_into(const double* grams, int N, int R, int n, double* sGam, int ovr_mode = -1,
+                                           const double* ovr = nullptr) {
     for (int e = threadIdx.x; e < R * R; e += kEpiThreads) {
         double g[CPG_MAX_MODES];
 #pragma unroll
-        for (int k = 0; k < CPG_MAX_MODES; ++k) g[k] = (k < N && k != n) ? a.grams[(int64_t)k * R * R + e] : 1.0;
+        for (int k = 0; k < CPG_MAX_MODES; ++k)
+            g[k] = (k < N && k != n) ? (k == ovr_mode ? ovr[e] : grams[(int64_t)k * R * R + e]) : 1.0;
         double v = 1.0;
 #pragma unroll
         for (int k = 0; k < CPG_MAX_MODES; ++k) v *= g[k];
         const int i = e / R;
         sGam[i * RT + (e - i * R)] = v;
     }
+}
+template <typename TC, int RT>
+__device__ __forceinline__ void block_gamma(const EpiArgs<TC>& a, int n, double* sGam) {
+    gamma_into<RT>(a.grams, a.fs.N, a.fs.R, n, sGam);
 }
 
 // Gram of a solved factor held as rows of stride RT (float64): entry (r, c)
@@ -397,13 +402,13 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // come from lane k by readlane, so a step needs no LDS and no barrier.  Every
 // wave with columns of G^T repeats the (small) elimination of Gamma', with
 // identical results.  *sFlag carries the outcome to the other waves.
+// I rows of G (stride RT) in sG; the solved rows are stored to A (I x R, when
+// not null) and, rounded to TC, to sF (stride RT).
 template <typename TC, int RT>
-__device__ __forceinline__ bool wave_eliminate(const EpiArgs<TC>& a, int n, const double* sG, const double* sGam,
+__device__ __forceinline__ bool wave_eliminate(int R, int64_t I, const double* sG, const double* sGam, TC* A,
                                                double* sF, int* sFlag) {
     constexpr int kSets = (kEpiGCap / RT + kEpiThreads - 1) / kEpiThreads;   // columns of G^T per lane
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-    const int R = a.fs.R;
-    const int64_t I = a.fs.dims[n];
     if ((int64_t)w * 64 < I) {
         double gc[RT], xc[kSets][RT];
 #pragma unroll
@@ -442,7 +447,6 @@ __device__ __forceinline__ bool wave_eliminate(const EpiArgs<TC>& a, int n, cons
             }
         }
         if (ok) {
-            TC* A = (TC*)a.fs.A[n];
 #pragma unroll
             for (int q = 0; q < kSets; ++q) {
                 const int64_t i = (int64_t)(q * (kEpiThreads / 64) + w) * 64 + l;
@@ -451,7 +455,7 @@ __device__ __forceinline__ bool wave_eliminate(const EpiArgs<TC>& a, int n, cons
                     for (int s = 0; s < RT; ++s) {
                         if (s < R) {
                             const TC v = (TC)xc[q][s];
-                            A[i * R + s] = v;
+                            if (A) A[i * R + s] = v;
                             sF[i * RT + s] = (double)v;   // the stored (rounded) factor, for its Gram
                         }
                     }
@@ -529,7 +533,7 @@ __device__ __forceinline__ bool block_solve(const EpiArgs<TC>& a, int n, double*
         __syncthreads();
     }
     if constexpr (RT <= 16) {
-        if (!wave_eliminate<TC, RT>(a, n, sG, sGam, sPub, sFlag)) return false;
+        if (!wave_eliminate<TC, RT>(R, I, sG, sGam, (TC*)a.fs.A[n], sPub, sFlag)) return false;
         CPG_EPI_MARK(22);
         if constexpr (RT == 16) {
             if (tid < 64) wave_gram16(sPub, I, R, a.grams + (int64_t)n * R * R);
@@ -733,6 +737,209 @@ __global__ __launch_bounds__(kEpiThreads) void k_epilogue(EpiArgs<TC> a0, EpiArg
         epilogue_body<TC, RT>(a0, sG, sGam, spart, sKR, spart4, &sFlag);
     else
         epilogue_body<TC, RT>(a1, sG, sGam, spart, sKR, spart4, &sFlag);
+}
+
+// ---------------------------------------------------------------------------
+// ALS update of a two-mode side on many blocks (eq. 2.14, Section 4 order).
+// Every block solves the side's first mode n1 from its precomputed gradient
+// (a small R x R system; all blocks reach identical results, block 0 stores
+// the factor and its Gram).  With the new A^(n1) the chain step of eq. 3.20 /
+// 3.22 is already the gradient of the last mode n2 (no Khatri-Rao block is
+// left), one row per output row, and the rows of A^(n2) = G^(n2) Gamma^{-1} are
+// independent: each block forms its slice of G^(n2) from the chain tensor,
+// solves it and stores it.  The last block to finish (ticket counter, device
+// fences around it) forms the Gram of the new A^(n2) and, on the left pass,
+// the cost of eq. 2.12 from the per-block partials of <Y, Yhat> in block order.
+// ---------------------------------------------------------------------------
+constexpr int kRowsTerms = 8;   // chain-tensor loads in flight per thread
+
+template <int RT>
+__global__ __launch_bounds__(kEpiThreads) void k_epi_rows(EpiRows a) {
+    __shared__ double sG[kEpiGCap];        // G^(n1), rows of stride RT
+    __shared__ double sF[kEpiGCap];        // new A^(n1) (rounded), later the new A^(n2)
+    __shared__ double sGam[RT * RT];
+    __shared__ double sGram1[RT * RT];     // Gram of the new A^(n1) (R x R)
+    __shared__ double sGram2[RT * RT];     // Gram of the new A^(n2) (last block)
+    static_assert(kEpiRowsCells <= kEpiThreads, "a slice's reduction fits the block");
+    __shared__ double sX[kEpiRowsCells];   // this block's rows of G^(n2), stride RT
+    __shared__ double sA2[kEpiRowsCells];  // ... and of the new A^(n2)
+    __shared__ d4 spart4[kEpiThreads];
+    __shared__ double spart[kEpiThreads];
+    __shared__ int sFlag, sLast;
+    const int tid = threadIdx.x;
+    const int R = a.fs.R, N = a.fs.N, ld = a.ld, nq = ld >> 2;
+    const int m1 = a.n1 - 1, m2 = a.n2 - 1;   // 0-based
+    const int64_t I1 = a.fs.dims[m1], I2 = a.fs.dims[m2];
+    float* A1 = (float*)a.fs.A[m1];
+    float* A2 = (float*)a.fs.A[m2];
+
+    // first mode: G^(n1) and Gamma^(n1), then the solve (one jittered retry)
+    for (int64_t o = tid; o < I1 * R; o += kEpiThreads) {
+        const int64_t i = o / R;
+        sG[i * RT + (o - i * R)] = (double)a.Gpre[o];
+    }
+    gamma_into<RT>(a.grams, N, R, m1, sGam);
+    __syncthreads();
+    bool ok1 = wave_eliminate<float, RT>(R, I1, sG, sGam, blockIdx.x == 0 ? A1 : nullptr, sF, &sFlag);
+    if (!ok1) {
+        gamma_into<RT>(a.grams, N, R, m1, sGam);
+        __syncthreads();
+        double tr = 0.0;
+        for (int c = 0; c < R; ++c) tr += sGam[c * RT + c];
+        __syncthreads();
+        if (tid < R) sGam[tid * RT + tid] += 1e-12 * tr / R;
+        __syncthreads();
+        ok1 = wave_eliminate<float, RT>(R, I1, sG, sGam, blockIdx.x == 0 ? A1 : nullptr, sF, &sFlag);
+    }
+    if (!ok1) {
+        // A^(n1) is kept: the chain step below uses it as it is
+        if (blockIdx.x == 0 && tid == 0) atomicOr(a.flags, 1);
+        for (int64_t o = tid; o < I1 * R; o += kEpiThreads) {
+            const int64_t i = o / R;
+            sF[i * RT + (o - i * R)] = (double)A1[o];
+        }
+        __syncthreads();
+    }
+    // Gram of A^(n1) as stored; block 0 publishes it
+    if constexpr (RT == 16) {
+        if (tid < 64) wave_gram16(sF, I1, R, sGram1);
+        __syncthreads();
+    } else {
+        block_gram_rows<RT>(sF, I1, R, sGram1, spart);
+    }
+    if (blockIdx.x == 0 && ok1)
+        for (int e = tid; e < R * R; e += kEpiThreads) a.grams[(int64_t)m1 * R * R + e] = sGram1[e];
+    gamma_into<RT>(a.grams, N, R, m2, sGam, m1, sGram1);
+
+    // this block's rows of G^(n2): G(i, r) = sum_j Z(row(i, j), r) A^(n1)(j, r),
+    // right: row = i + I2 j, left: row = j + I1 i; float64 sums rounded to float
+    // (as a stored chain tensor), terms j in order per thread, thread parts in order
+    const int64_t r0 = (int64_t)blockIdx.x * a.rows;
+    const int nrows = (int)min((int64_t)a.rows, I2 - r0);
+    const int nout = nrows * nq;
+    const int parts = kEpiThreads / nout;
+    {
+        d4 acc{0.0, 0.0, 0.0, 0.0};
+        if (tid < parts * nout) {
+            const int o = tid % nout, part = tid / nout;
+            const int64_t i = r0 + o / nq;
+            const int q = o - (o / nq) * nq;
+            const int64_t rs = a.side == 0 ? I2 : 1;           // row stride of term j
+            const int64_t rb = a.side == 0 ? i : I1 * i;       // row of term 0
+            const float* src = a.Z + rb * ld + 4 * q;
+            for (int64_t j0 = part; j0 < I1; j0 += (int64_t)kRowsTerms * parts) {
+                float4 v[kRowsTerms];
+#pragma unroll
+                for (int u = 0; u < kRowsTerms; ++u) {
+                    const int64_t j = min(j0 + (int64_t)u * parts, I1 - 1);
+                    v[u] = *(const float4*)(src + j * rs * ld);
+                }
+#pragma unroll
+                for (int u = 0; u < kRowsTerms; ++u) {
+                    const int64_t j = j0 + (int64_t)u * parts;
+                    if (j < I1) {
+                        const double* w = sF + j * RT + 4 * q;
+                        acc = acc + d4{(double)v[u].x * w[0], (double)v[u].y * w[1], (double)v[u].z * w[2],
+                                       (double)v[u].w * w[3]};
+                    }
+                }
+            }
+        }
+        spart4[tid] = acc;
+        __syncthreads();
+        if (tid < nout) {
+            d4 t{0.0, 0.0, 0.0, 0.0};
+            for (int pp = 0; pp < parts; ++pp) t = t + spart4[pp * nout + tid];
+            const int il = tid / nq, q = tid - (tid / nq) * nq;
+            const double tv[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) sX[il * RT + 4 * q + u] = (double)(float)tv[u];
+        }
+        __syncthreads();
+    }
+
+    // solve the slice: A^(n2) rows = G^(n2) rows Gamma^{-1} (the same pivots in every block)
+    bool ok2 = wave_eliminate<float, RT>(R, nrows, sX, sGam, A2 + r0 * R, sA2, &sFlag);
+    if (!ok2) {
+        gamma_into<RT>(a.grams, N, R, m2, sGam, m1, sGram1);
+        __syncthreads();
+        double tr = 0.0;
+        for (int c = 0; c < R; ++c) tr += sGam[c * RT + c];
+        __syncthreads();
+        if (tid < R) sGam[tid * RT + tid] += 1e-12 * tr / R;
+        __syncthreads();
+        ok2 = wave_eliminate<float, RT>(R, nrows, sX, sGam, A2 + r0 * R, sA2, &sFlag);
+    }
+    if (!ok2 && tid == 0) atomicOr(a.flags, 1);
+    // cost partial: sum over this slice of G^(n2) .* A^(n2) as stored (the factor
+    // kept on a failed solve)
+    if (a.cost) {
+        double acc = 0.0;
+        for (int e = tid; e < nrows * R; e += kEpiThreads) {
+            const int il = e / R, c = e - (e / R) * R;
+            const double av = ok2 ? sA2[il * RT + c] : (double)A2[(r0 + il) * R + c];
+            acc += sX[il * RT + c] * av;
+        }
+        const double inner = block_sum(acc, spart);
+        if (tid == 0) a.part[blockIdx.x] = inner;
+    }
+
+    // the last block to finish
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) sLast = atomicAdd(a.ticket, 1) == (int)gridDim.x - 1 ? 1 : 0;
+    __syncthreads();
+    if (!sLast) return;
+    __threadfence();
+    for (int64_t o = tid; o < I2 * R; o += kEpiThreads) {
+        const int64_t i = o / R;
+        sF[i * RT + (o - i * R)] = (double)__builtin_nontemporal_load(A2 + o);
+    }
+    __syncthreads();
+    if constexpr (RT == 16) {
+        if (tid < 64) wave_gram16(sF, I2, R, sGram2);
+        __syncthreads();
+    } else {
+        block_gram_rows<RT>(sF, I2, R, sGram2, spart);
+    }
+    for (int e = tid; e < R * R; e += kEpiThreads) a.grams[(int64_t)m2 * R * R + e] = sGram2[e];
+    if (a.cost) {
+        // eq. 2.12: D = ||Y||^2 - 2 <Y, Yhat> + ||Yhat||^2, <Y, Yhat> = sum G^(N) .* A^(N)
+        double inner = 0.0;
+        for (int b = 0; b < (int)gridDim.x; ++b) inner += __builtin_nontemporal_load(a.part + b);
+        double h = 0.0;
+        for (int e = tid; e < R * R; e += kEpiThreads) {
+            double v = 1.0;
+            for (int k = 0; k < N; ++k)
+                v *= k == m1 ? sGram1[e] : (k == m2 ? sGram2[e] : a.grams[(int64_t)k * R * R + e]);
+            h += v;
+        }
+        const double nrm = block_sum(h, spart);
+        if (tid == 0) {
+            const double y2 = a.scal[0];
+            const double D = y2 - 2.0 * inner + nrm;
+            a.scal[2] = D;
+            a.scal[3] = 1.0 - sqrt(D > 0.0 ? D : 0.0) / sqrt(y2);
+            a.scal[4] = inner;
+            a.scal[5] = nrm;
+            if (!isfinite(D)) atomicOr(a.flags, 2);
+        }
+    }
+    if (tid == 0) *a.ticket = 0;
+}
+
+hipError_t launch_epi_rows(const EpiRows& a, hipStream_t s) {
+    const int64_t I2 = a.fs.dims[a.n2 - 1];
+    const int64_t nb = (I2 + a.rows - 1) / a.rows;
+    const int rt = a.fs.R <= 4 ? 4 : 16;
+    if (a.fs.R > 16 || nb < 1 || nb > kEpiRowsMaxBlocks || (int64_t)a.rows * rt > kEpiRowsCells ||
+        a.fs.dims[a.n1 - 1] * rt > kEpiGCap || I2 * rt > kEpiGCap || (a.ld & 3) != 0)
+        return hipErrorInvalidValue;
+    if (rt == 4)
+        hipLaunchKernelGGL(k_epi_rows<4>, dim3((unsigned)nb), dim3(kEpiThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_epi_rows<16>, dim3((unsigned)nb), dim3(kEpiThreads), 0, s, a);
+    return hipGetLastError();
 }
 
 template <typename TC>
