@@ -692,8 +692,9 @@ static int als_sweep_core(cpgrad_plan_s* p, const void* Y, void* const* A) {
     bool pre = false;
     int st = finish_partials(p, fsf, p->t_right, 1, p->Gtmp, nullptr, true, &pre, nullptr, p->flags);
     if (st) return st;
-    if (epi && pre && rows_side_ok(p, 0))
-        st = run_rows(p, fs.f, 0, false);
+    const bool rows_r = epi && pre && rows_side_ok(p, 0);
+    if (rows_r)
+        st = run_rows(p, fs.f, 0, false);   // leaves the Gram of A^(1) to the left pass's reduction
     else if (epi)
         st = p->fdt == CPG_F64 ? run_side<double>(p, fs.d, 0, A, nullptr, true, true, false)
                                : run_side<float>(p, fs.f, 0, A, nullptr, true, true, false,
@@ -703,7 +704,7 @@ static int als_sweep_core(cpgrad_plan_s* p, const void* Y, void* const* A) {
     if (st) return st;
     // pass 2 over Y: P_L with the updated A^(1..n*), then modes n*+1, ..., N and the cost
     CPG_TRY(run_contract(p, Y, fs, p->t_left, 2));
-    st = finish_partials(p, fsf, p->t_left, 2, nullptr, p->Gtmp, false, &pre);
+    st = finish_partials(p, fsf, p->t_left, 2, nullptr, p->Gtmp, rows_r, &pre);
     if (st) return st;
     if (epi && pre && rows_side_ok(p, 1)) {
         st = run_rows(p, fs.f, 1, true);

@@ -22,6 +22,9 @@
 #ifndef CPG_EPI_WMARK
 #define CPG_EPI_WMARK(k)
 #endif
+#ifndef CPG_ROWS_MARK
+#define CPG_ROWS_MARK(k)
+#endif
 
 namespace cpg {
 
@@ -747,9 +750,11 @@ __global__ __launch_bounds__(kEpiThreads) void k_epilogue(EpiArgs<TC> a0, EpiArg
 // 3.22 is already the gradient of the last mode n2 (no Khatri-Rao block is
 // left), one row per output row, and the rows of A^(n2) = G^(n2) Gamma^{-1} are
 // independent: each block forms its slice of G^(n2) from the chain tensor,
-// solves it and stores it.  The last block to finish (ticket counter, device
-// fences around it) forms the Gram of the new A^(n2) and, on the left pass,
-// the cost of eq. 2.12 from the per-block partials of <Y, Yhat> in block order.
+// solves it and stores it.  On the pass that ends the sweep, the last block to
+// finish (ticket counter, device fences around it) forms the Gram of the new
+// A^(n2) and the cost of eq. 2.12 from the per-block partials of <Y, Yhat> in
+// block order; otherwise the Grams of the side are left to the next pass's
+// reduction, which recomputes every Gram.
 // ---------------------------------------------------------------------------
 constexpr int kRowsTerms = 8;   // chain-tensor loads in flight per thread
 
@@ -760,6 +765,7 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_rows(EpiRows a) {
     __shared__ double sGam[RT * RT];
     __shared__ double sGram1[RT * RT];     // Gram of the new A^(n1) (R x R)
     __shared__ double sGram2[RT * RT];     // Gram of the new A^(n2) (last block)
+    __shared__ double sP[RT * RT];         // Hadamard product of the Grams of the other modes (R x R)
     static_assert(kEpiRowsCells <= kEpiThreads, "a slice's reduction fits the block");
     __shared__ double sX[kEpiRowsCells];   // this block's rows of G^(n2), stride RT
     __shared__ double sA2[kEpiRowsCells];  // ... and of the new A^(n2)
@@ -772,23 +778,42 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_rows(EpiRows a) {
     const int64_t I1 = a.fs.dims[m1], I2 = a.fs.dims[m2];
     float* A1 = (float*)a.fs.A[m1];
     float* A2 = (float*)a.fs.A[m2];
+    CPG_ROWS_MARK(0);
+    // Gamma of a mode of this side = sP .* (the other mode's Gram), eq. 2.14;
+    // `jitter` adds 1e-12 tr(Gamma)/R to the diagonal (the retry)
+    auto form_gamma = [&](const double* g, bool jitter) {
+        __syncthreads();
+        for (int e = tid; e < R * R; e += kEpiThreads) {
+            const int i = e / R;
+            sGam[i * RT + (e - i * R)] = sP[e] * g[e];
+        }
+        __syncthreads();
+        if (jitter) {
+            double tr = 0.0;
+            for (int c = 0; c < R; ++c) tr += sGam[c * RT + c];
+            __syncthreads();
+            if (tid < R) sGam[tid * RT + tid] += 1e-12 * tr / R;
+            __syncthreads();
+        }
+    };
 
-    // first mode: G^(n1) and Gamma^(n1), then the solve (one jittered retry)
+    // first mode: G^(n1), the Grams (one round of loads), then the solve (one jittered retry)
     for (int64_t o = tid; o < I1 * R; o += kEpiThreads) {
         const int64_t i = o / R;
         sG[i * RT + (o - i * R)] = (double)a.Gpre[o];
     }
-    gamma_into<RT>(a.grams, N, R, m1, sGam);
-    __syncthreads();
+    for (int e = tid; e < R * R; e += kEpiThreads) {
+        double v = 1.0;
+        for (int k = 0; k < N; ++k)
+            if (k != m1 && k != m2) v *= a.grams[(int64_t)k * R * R + e];
+        sP[e] = v;
+        sGram2[e] = a.grams[(int64_t)m2 * R * R + e];   // Gram of A^(n2) before its update
+    }
+    form_gamma(sGram2, false);
     bool ok1 = wave_eliminate<float, RT>(R, I1, sG, sGam, blockIdx.x == 0 ? A1 : nullptr, sF, &sFlag);
+    CPG_ROWS_MARK(1);
     if (!ok1) {
-        gamma_into<RT>(a.grams, N, R, m1, sGam);
-        __syncthreads();
-        double tr = 0.0;
-        for (int c = 0; c < R; ++c) tr += sGam[c * RT + c];
-        __syncthreads();
-        if (tid < R) sGam[tid * RT + tid] += 1e-12 * tr / R;
-        __syncthreads();
+        form_gamma(sGram2, true);
         ok1 = wave_eliminate<float, RT>(R, I1, sG, sGam, blockIdx.x == 0 ? A1 : nullptr, sF, &sFlag);
     }
     if (!ok1) {
@@ -809,7 +834,8 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_rows(EpiRows a) {
     }
     if (blockIdx.x == 0 && ok1)
         for (int e = tid; e < R * R; e += kEpiThreads) a.grams[(int64_t)m1 * R * R + e] = sGram1[e];
-    gamma_into<RT>(a.grams, N, R, m2, sGam, m1, sGram1);
+    form_gamma(sGram1, false);
+    CPG_ROWS_MARK(2);
 
     // this block's rows of G^(n2): G(i, r) = sum_j Z(row(i, j), r) A^(n1)(j, r),
     // right: row = i + I2 j, left: row = j + I1 i; float64 sums rounded to float
@@ -857,20 +883,16 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_rows(EpiRows a) {
         }
         __syncthreads();
     }
+    CPG_ROWS_MARK(3);
 
     // solve the slice: A^(n2) rows = G^(n2) rows Gamma^{-1} (the same pivots in every block)
     bool ok2 = wave_eliminate<float, RT>(R, nrows, sX, sGam, A2 + r0 * R, sA2, &sFlag);
     if (!ok2) {
-        gamma_into<RT>(a.grams, N, R, m2, sGam, m1, sGram1);
-        __syncthreads();
-        double tr = 0.0;
-        for (int c = 0; c < R; ++c) tr += sGam[c * RT + c];
-        __syncthreads();
-        if (tid < R) sGam[tid * RT + tid] += 1e-12 * tr / R;
-        __syncthreads();
+        form_gamma(sGram1, true);
         ok2 = wave_eliminate<float, RT>(R, nrows, sX, sGam, A2 + r0 * R, sA2, &sFlag);
     }
     if (!ok2 && tid == 0) atomicOr(a.flags, 1);
+    CPG_ROWS_MARK(4);
     // cost partial: sum over this slice of G^(n2) .* A^(n2) as stored (the factor
     // kept on a failed solve)
     if (a.cost) {
@@ -883,14 +905,18 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_rows(EpiRows a) {
         const double inner = block_sum(acc, spart);
         if (tid == 0) a.part[blockIdx.x] = inner;
     }
+    CPG_ROWS_MARK(5);
 
-    // the last block to finish
+    // the last block to finish forms the new Gram of A^(n2) and the cost (the
+    // pass without the cost ends here: the next pass recomputes the Grams)
+    if (!a.cost) return;
     __threadfence();
     __syncthreads();
     if (tid == 0) sLast = atomicAdd(a.ticket, 1) == (int)gridDim.x - 1 ? 1 : 0;
     __syncthreads();
     if (!sLast) return;
     __threadfence();
+    CPG_ROWS_MARK(6);
     for (int64_t o = tid; o < I2 * R; o += kEpiThreads) {
         const int64_t i = o / R;
         sF[i * RT + (o - i * R)] = (double)__builtin_nontemporal_load(A2 + o);
@@ -903,17 +929,12 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_rows(EpiRows a) {
         block_gram_rows<RT>(sF, I2, R, sGram2, spart);
     }
     for (int e = tid; e < R * R; e += kEpiThreads) a.grams[(int64_t)m2 * R * R + e] = sGram2[e];
-    if (a.cost) {
+    {
         // eq. 2.12: D = ||Y||^2 - 2 <Y, Yhat> + ||Yhat||^2, <Y, Yhat> = sum G^(N) .* A^(N)
         double inner = 0.0;
         for (int b = 0; b < (int)gridDim.x; ++b) inner += __builtin_nontemporal_load(a.part + b);
         double h = 0.0;
-        for (int e = tid; e < R * R; e += kEpiThreads) {
-            double v = 1.0;
-            for (int k = 0; k < N; ++k)
-                v *= k == m1 ? sGram1[e] : (k == m2 ? sGram2[e] : a.grams[(int64_t)k * R * R + e]);
-            h += v;
-        }
+        for (int e = tid; e < R * R; e += kEpiThreads) h += sP[e] * sGram1[e] * sGram2[e];
         const double nrm = block_sum(h, spart);
         if (tid == 0) {
             const double y2 = a.scal[0];
@@ -926,6 +947,7 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_rows(EpiRows a) {
         }
     }
     if (tid == 0) *a.ticket = 0;
+    CPG_ROWS_MARK(7);
 }
 
 hipError_t launch_epi_rows(const EpiRows& a, hipStream_t s) {
