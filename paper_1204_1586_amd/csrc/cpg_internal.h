@@ -73,7 +73,6 @@ struct EpiRows {
     double* grams;         // [N][R][R], read; grams[n1], grams[n2] written
     double* scal;          // as in EpiArgs
     int* flags;            // bit 0: not SPD, bit 1: non-finite cost
-    int* ticket;           // zero between launches; the last block to finish resets it
     double* part;          // one float64 per block (cost partials)
 };
 constexpr int kEpiRowsMaxBlocks = 16;

@@ -42,7 +42,7 @@ struct cpgrad_plan_s {
     double* grams = nullptr;
     double* scal = nullptr;   // [0]=||Y||^2 [2]=cost [3]=fit [4]=inner [5]=||Yhat||^2 [6]=inner(cp_fit)
     double* red = nullptr;    // reduction scratch (1024 doubles)
-    int* flags = nullptr;     // [0] status bits, [8] ticket of the many-block ALS epilogue
+    int* flags = nullptr;     // [0] status bits
     double* rpart = nullptr;  // per-block cost partials of the many-block ALS epilogue
     double* host = nullptr;   // pinned readback: scal[0..7], flags
     const void* bound = nullptr;
@@ -672,7 +672,6 @@ static int run_rows(cpgrad_plan_s* p, const FacSet<float>& fs, int side, bool co
     e.grams = p->grams;
     e.scal = p->scal;
     e.flags = p->flags;
-    e.ticket = p->flags + 8;
     e.part = p->rpart;
     CPG_TRY(launch_epi_rows(e, p->stream));
     return CPG_OK;

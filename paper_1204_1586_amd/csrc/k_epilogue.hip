@@ -750,11 +750,10 @@ __global__ __launch_bounds__(kEpiThreads) void k_epilogue(EpiArgs<TC> a0, EpiArg
 // 3.22 is already the gradient of the last mode n2 (no Khatri-Rao block is
 // left), one row per output row, and the rows of A^(n2) = G^(n2) Gamma^{-1} are
 // independent: each block forms its slice of G^(n2) from the chain tensor,
-// solves it and stores it.  On the pass that ends the sweep, the last block to
-// finish (ticket counter, device fences around it) forms the Gram of the new
-// A^(n2) and the cost of eq. 2.12 from the per-block partials of <Y, Yhat> in
-// block order; otherwise the Grams of the side are left to the next pass's
-// reduction, which recomputes every Gram.
+// solves it and stores it, with its partial of <Y, Yhat> when the pass ends
+// the sweep (k_epi_rows_cost then forms the new Gram of A^(n2) and the cost).
+// Otherwise the Gram of A^(n2) is left to the next pass's reduction, which
+// recomputes every Gram.
 // ---------------------------------------------------------------------------
 constexpr int kRowsTerms = 8;   // chain-tensor loads in flight per thread
 
@@ -771,7 +770,7 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_rows(EpiRows a) {
     __shared__ double sA2[kEpiRowsCells];  // ... and of the new A^(n2)
     __shared__ d4 spart4[kEpiThreads];
     __shared__ double spart[kEpiThreads];
-    __shared__ int sFlag, sLast;
+    __shared__ int sFlag;
     const int tid = threadIdx.x;
     const int R = a.fs.R, N = a.fs.N, ld = a.ld, nq = ld >> 2;
     const int m1 = a.n1 - 1, m2 = a.n2 - 1;   // 0-based
@@ -779,6 +778,25 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_rows(EpiRows a) {
     float* A1 = (float*)a.fs.A[m1];
     float* A2 = (float*)a.fs.A[m2];
     CPG_ROWS_MARK(0);
+    // the first batch of this block's chain-tensor loads (below) goes out now:
+    // the addresses do not depend on the solve of the first mode
+    const int64_t r0 = (int64_t)blockIdx.x * a.rows;
+    const int nrows = (int)min((int64_t)a.rows, I2 - r0);
+    const int nout = nrows * nq;
+    const int parts = kEpiThreads / nout;
+    const int o_t = tid % nout, part_t = tid / nout;
+    const int64_t i_t = r0 + o_t / nq;
+    const int q_t = o_t - (o_t / nq) * nq;
+    const int64_t rs = a.side == 0 ? I2 : 1;              // row stride of term j
+    const float* zsrc = a.Z + (a.side == 0 ? i_t : I1 * i_t) * ld + 4 * q_t;
+    float4 zv[kRowsTerms];
+    if (tid < parts * nout) {
+#pragma unroll
+        for (int u = 0; u < kRowsTerms; ++u) {
+            const int64_t j = min((int64_t)part_t + (int64_t)u * parts, I1 - 1);
+            zv[u] = *(const float4*)(zsrc + j * rs * ld);
+        }
+    }
     // Gamma of a mode of this side = sP .* (the other mode's Gram), eq. 2.14;
     // `jitter` adds 1e-12 tr(Gamma)/R to the diagonal (the retry)
     auto form_gamma = [&](const double* g, bool jitter) {
@@ -840,33 +858,24 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_rows(EpiRows a) {
     // this block's rows of G^(n2): G(i, r) = sum_j Z(row(i, j), r) A^(n1)(j, r),
     // right: row = i + I2 j, left: row = j + I1 i; float64 sums rounded to float
     // (as a stored chain tensor), terms j in order per thread, thread parts in order
-    const int64_t r0 = (int64_t)blockIdx.x * a.rows;
-    const int nrows = (int)min((int64_t)a.rows, I2 - r0);
-    const int nout = nrows * nq;
-    const int parts = kEpiThreads / nout;
     {
         d4 acc{0.0, 0.0, 0.0, 0.0};
         if (tid < parts * nout) {
-            const int o = tid % nout, part = tid / nout;
-            const int64_t i = r0 + o / nq;
-            const int q = o - (o / nq) * nq;
-            const int64_t rs = a.side == 0 ? I2 : 1;           // row stride of term j
-            const int64_t rb = a.side == 0 ? i : I1 * i;       // row of term 0
-            const float* src = a.Z + rb * ld + 4 * q;
-            for (int64_t j0 = part; j0 < I1; j0 += (int64_t)kRowsTerms * parts) {
-                float4 v[kRowsTerms];
+            for (int64_t j0 = part_t; j0 < I1; j0 += (int64_t)kRowsTerms * parts) {
+                if (j0 != part_t) {   // batches after the preloaded one
 #pragma unroll
-                for (int u = 0; u < kRowsTerms; ++u) {
-                    const int64_t j = min(j0 + (int64_t)u * parts, I1 - 1);
-                    v[u] = *(const float4*)(src + j * rs * ld);
+                    for (int u = 0; u < kRowsTerms; ++u) {
+                        const int64_t j = min(j0 + (int64_t)u * parts, I1 - 1);
+                        zv[u] = *(const float4*)(zsrc + j * rs * ld);
+                    }
                 }
 #pragma unroll
                 for (int u = 0; u < kRowsTerms; ++u) {
                     const int64_t j = j0 + (int64_t)u * parts;
                     if (j < I1) {
-                        const double* w = sF + j * RT + 4 * q;
-                        acc = acc + d4{(double)v[u].x * w[0], (double)v[u].y * w[1], (double)v[u].z * w[2],
-                                       (double)v[u].w * w[3]};
+                        const double* w = sF + j * RT + 4 * q_t;
+                        acc = acc + d4{(double)zv[u].x * w[0], (double)zv[u].y * w[1], (double)zv[u].z * w[2],
+                                       (double)zv[u].w * w[3]};
                     }
                 }
             }
@@ -874,8 +883,17 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_rows(EpiRows a) {
         spart4[tid] = acc;
         __syncthreads();
         if (tid < nout) {
+            // the parts in order, eight LDS reads in flight
             d4 t{0.0, 0.0, 0.0, 0.0};
-            for (int pp = 0; pp < parts; ++pp) t = t + spart4[pp * nout + tid];
+            int pp = 0;
+            for (; pp + 8 <= parts; pp += 8) {
+                d4 u[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) u[k] = spart4[(pp + k) * nout + tid];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) t = t + u[k];
+            }
+            for (; pp < parts; ++pp) t = t + spart4[pp * nout + tid];
             const int il = tid / nq, q = tid - (tid / nq) * nq;
             const double tv[4] = {t.x, t.y, t.z, t.w};
 #pragma unroll
@@ -906,21 +924,34 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_rows(EpiRows a) {
         if (tid == 0) a.part[blockIdx.x] = inner;
     }
     CPG_ROWS_MARK(5);
+}
 
-    // the last block to finish forms the new Gram of A^(n2) and the cost (the
-    // pass without the cost ends here: the next pass recomputes the Grams)
-    if (!a.cost) return;
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) sLast = atomicAdd(a.ticket, 1) == (int)gridDim.x - 1 ? 1 : 0;
-    __syncthreads();
-    if (!sLast) return;
-    __threadfence();
-    CPG_ROWS_MARK(6);
+// The end of the pass that closes a sweep, one block after k_epi_rows: the
+// Gram of the new A^(n2) and the cost of eq. 2.12 from the per-block partials
+// of <Y, Yhat> (block order) and the Grams of all modes.
+template <int RT>
+__global__ __launch_bounds__(kEpiThreads) void k_epi_rows_cost(EpiRows a, int nblocks) {
+    __shared__ double sF[kEpiGCap];
+    __shared__ double sGram2[RT * RT];
+    __shared__ double sP[RT * RT];
+    __shared__ double spart[kEpiThreads];
+    const int tid = threadIdx.x;
+    const int R = a.fs.R, N = a.fs.N;
+    const int m2 = a.n2 - 1;
+    const int64_t I2 = a.fs.dims[m2];
+    const float* A2 = a.fs.A[m2];
     for (int64_t o = tid; o < I2 * R; o += kEpiThreads) {
         const int64_t i = o / R;
-        sF[i * RT + (o - i * R)] = (double)__builtin_nontemporal_load(A2 + o);
+        sF[i * RT + (o - i * R)] = (double)A2[o];
     }
+    for (int e = tid; e < R * R; e += kEpiThreads) {
+        double v = 1.0;
+        for (int k = 0; k < N; ++k)
+            if (k != m2) v *= a.grams[(int64_t)k * R * R + e];
+        sP[e] = v;
+    }
+    double inner = 0.0;
+    for (int b = 0; b < nblocks; ++b) inner += a.part[b];
     __syncthreads();
     if constexpr (RT == 16) {
         if (tid < 64) wave_gram16(sF, I2, R, sGram2);
@@ -929,25 +960,19 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_rows(EpiRows a) {
         block_gram_rows<RT>(sF, I2, R, sGram2, spart);
     }
     for (int e = tid; e < R * R; e += kEpiThreads) a.grams[(int64_t)m2 * R * R + e] = sGram2[e];
-    {
-        // eq. 2.12: D = ||Y||^2 - 2 <Y, Yhat> + ||Yhat||^2, <Y, Yhat> = sum G^(N) .* A^(N)
-        double inner = 0.0;
-        for (int b = 0; b < (int)gridDim.x; ++b) inner += __builtin_nontemporal_load(a.part + b);
-        double h = 0.0;
-        for (int e = tid; e < R * R; e += kEpiThreads) h += sP[e] * sGram1[e] * sGram2[e];
-        const double nrm = block_sum(h, spart);
-        if (tid == 0) {
-            const double y2 = a.scal[0];
-            const double D = y2 - 2.0 * inner + nrm;
-            a.scal[2] = D;
-            a.scal[3] = 1.0 - sqrt(D > 0.0 ? D : 0.0) / sqrt(y2);
-            a.scal[4] = inner;
-            a.scal[5] = nrm;
-            if (!isfinite(D)) atomicOr(a.flags, 2);
-        }
+    // eq. 2.12: D = ||Y||^2 - 2 <Y, Yhat> + ||Yhat||^2, <Y, Yhat> = sum G^(N) .* A^(N)
+    double h = 0.0;
+    for (int e = tid; e < R * R; e += kEpiThreads) h += sP[e] * sGram2[e];
+    const double nrm = block_sum(h, spart);
+    if (tid == 0) {
+        const double y2 = a.scal[0];
+        const double D = y2 - 2.0 * inner + nrm;
+        a.scal[2] = D;
+        a.scal[3] = 1.0 - sqrt(D > 0.0 ? D : 0.0) / sqrt(y2);
+        a.scal[4] = inner;
+        a.scal[5] = nrm;
+        if (!isfinite(D)) atomicOr(a.flags, 2);
     }
-    if (tid == 0) *a.ticket = 0;
-    CPG_ROWS_MARK(7);
 }
 
 hipError_t launch_epi_rows(const EpiRows& a, hipStream_t s) {
@@ -957,10 +982,13 @@ hipError_t launch_epi_rows(const EpiRows& a, hipStream_t s) {
     if (a.fs.R > 16 || nb < 1 || nb > kEpiRowsMaxBlocks || (int64_t)a.rows * rt > kEpiRowsCells ||
         a.fs.dims[a.n1 - 1] * rt > kEpiGCap || I2 * rt > kEpiGCap || (a.ld & 3) != 0)
         return hipErrorInvalidValue;
-    if (rt == 4)
+    if (rt == 4) {
         hipLaunchKernelGGL(k_epi_rows<4>, dim3((unsigned)nb), dim3(kEpiThreads), 0, s, a);
-    else
+        if (a.cost) hipLaunchKernelGGL(k_epi_rows_cost<4>, dim3(1), dim3(kEpiThreads), 0, s, a, (int)nb);
+    } else {
         hipLaunchKernelGGL(k_epi_rows<16>, dim3((unsigned)nb), dim3(kEpiThreads), 0, s, a);
+        if (a.cost) hipLaunchKernelGGL(k_epi_rows_cost<16>, dim3(1), dim3(kEpiThreads), 0, s, a, (int)nb);
+    }
     return hipGetLastError();
 }
 
