@@ -60,7 +60,9 @@ hipError_t launch_epilogue(int fdt, int R, const void* args, int nsides, hipStre
 // factors, R <= 16): the side's first mode n1 from its precomputed gradient,
 // then the last mode n2, whose gradient is the chain step of the first
 // (eq. 3.20: right, n2 = 1; eq. 3.22: left, n2 = N) and whose rows are
-// independent: block b forms and solves rows [b rows, (b + 1) rows).
+// independent: block b forms and solves rows [b rows, (b + 1) rows).  The
+// Gram of the new A^(n2) is not formed (the next pass's reduction forms every
+// Gram); with `cost` a second launch adds up the cost of eq. 2.12.
 struct EpiRows {
     FacSet<float> fs;
     int side;              // 0 = right (n2 = n1 - 1 = 1), 1 = left (n2 = n1 + 1 = N)
@@ -73,7 +75,7 @@ struct EpiRows {
     double* grams;         // [N][R][R], read; grams[n1], grams[n2] written
     double* scal;          // as in EpiArgs
     int* flags;            // bit 0: not SPD, bit 1: non-finite cost
-    double* part;          // one float64 per block (cost partials)
+    double* part;          // two float64 per block (cost partials)
 };
 constexpr int kEpiRowsMaxBlocks = 16;
 constexpr int kEpiRowsCells = 512;   // rows x rank tile of one block's slice

@@ -183,7 +183,7 @@ static int configure(cpgrad_plan_s* p) {
     const size_t oS = off;      off += al(16 * 8);
     const size_t oRed = off;    off += al(kRedScratch * 8);
     const size_t oF = off;      off += al(16 * sizeof(int));
-    const size_t oRp = off;     off += al(kEpiRowsMaxBlocks * 8);
+    const size_t oRp = off;     off += al(2 * kEpiRowsMaxBlocks * 8);
     if (off > p->ws_bytes) {
         release(p);
         void* mem = nullptr;

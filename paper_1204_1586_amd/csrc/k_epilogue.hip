@@ -750,10 +750,9 @@ __global__ __launch_bounds__(kEpiThreads) void k_epilogue(EpiArgs<TC> a0, EpiArg
 // 3.22 is already the gradient of the last mode n2 (no Khatri-Rao block is
 // left), one row per output row, and the rows of A^(n2) = G^(n2) Gamma^{-1} are
 // independent: each block forms its slice of G^(n2) from the chain tensor,
-// solves it and stores it, with its partial of <Y, Yhat> when the pass ends
-// the sweep (k_epi_rows_cost then forms the new Gram of A^(n2) and the cost).
-// Otherwise the Gram of A^(n2) is left to the next pass's reduction, which
-// recomputes every Gram.
+// solves it and stores it, with its partials of the cost when the pass ends
+// the sweep (k_epi_rows_cost then adds them up).  The Gram of A^(n2) is left
+// to the next pass's reduction, which recomputes every Gram.
 // ---------------------------------------------------------------------------
 constexpr int kRowsTerms = 8;   // chain-tensor loads in flight per thread
 
@@ -911,68 +910,56 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_rows(EpiRows a) {
     }
     if (!ok2 && tid == 0) atomicOr(a.flags, 1);
     CPG_ROWS_MARK(4);
-    // cost partial: sum over this slice of G^(n2) .* A^(n2) as stored (the factor
-    // kept on a failed solve)
+    // cost partials of this slice (eq. 2.12), with A^(n2) as stored (the factor
+    // kept on a failed solve): <Y, Yhat> part = sum G^(n2) .* A^(n2), and the
+    // ||Yhat||^2 part = sum over its rows a of a^T S a, S = Hadamard product of
+    // the other modes' Grams (that of A^(n1) new), since Gram(A^(n2)) is the sum
+    // of a a^T over the rows
     if (a.cost) {
-        double acc = 0.0;
+        if (!ok2) {
+            for (int e = tid; e < nrows * R; e += kEpiThreads) {
+                const int il = e / R, c = e - (e / R) * R;
+                sA2[il * RT + c] = (double)A2[(r0 + il) * R + c];
+            }
+            __syncthreads();
+        }
+        double acc = 0.0, quad = 0.0;
         for (int e = tid; e < nrows * R; e += kEpiThreads) {
-            const int il = e / R, c = e - (e / R) * R;
-            const double av = ok2 ? sA2[il * RT + c] : (double)A2[(r0 + il) * R + c];
-            acc += sX[il * RT + c] * av;
+            const int il = e / R, r = e - (e / R) * R;
+            const double ar = sA2[il * RT + r];
+            acc += sX[il * RT + r] * ar;
+            double t = 0.0;
+            for (int c = 0; c < R; ++c) t += sP[r * R + c] * sGram1[r * R + c] * sA2[il * RT + c];
+            quad += ar * t;
         }
         const double inner = block_sum(acc, spart);
-        if (tid == 0) a.part[blockIdx.x] = inner;
+        const double h = block_sum(quad, spart);
+        if (tid == 0) {
+            a.part[2 * blockIdx.x] = inner;
+            a.part[2 * blockIdx.x + 1] = h;
+        }
     }
     CPG_ROWS_MARK(5);
 }
 
-// The end of the pass that closes a sweep, one block after k_epi_rows: the
-// Gram of the new A^(n2) and the cost of eq. 2.12 from the per-block partials
-// of <Y, Yhat> (block order) and the Grams of all modes.
-template <int RT>
-__global__ __launch_bounds__(kEpiThreads) void k_epi_rows_cost(EpiRows a, int nblocks) {
-    __shared__ double sF[kEpiGCap];
-    __shared__ double sGram2[RT * RT];
-    __shared__ double sP[RT * RT];
-    __shared__ double spart[kEpiThreads];
-    const int tid = threadIdx.x;
-    const int R = a.fs.R, N = a.fs.N;
-    const int m2 = a.n2 - 1;
-    const int64_t I2 = a.fs.dims[m2];
-    const float* A2 = a.fs.A[m2];
-    for (int64_t o = tid; o < I2 * R; o += kEpiThreads) {
-        const int64_t i = o / R;
-        sF[i * RT + (o - i * R)] = (double)A2[o];
+// The end of the pass that closes a sweep, one small kernel after k_epi_rows:
+// the cost of eq. 2.12 and the fit from the per-block partials (block order).
+// The Gram of the new A^(n2) is left to the next pass's reduction.
+__global__ void k_epi_rows_cost(EpiRows a, int nblocks) {
+    if (threadIdx.x != 0) return;
+    double inner = 0.0, nrm = 0.0;
+    for (int b = 0; b < nblocks; ++b) {
+        inner += a.part[2 * b];
+        nrm += a.part[2 * b + 1];
     }
-    for (int e = tid; e < R * R; e += kEpiThreads) {
-        double v = 1.0;
-        for (int k = 0; k < N; ++k)
-            if (k != m2) v *= a.grams[(int64_t)k * R * R + e];
-        sP[e] = v;
-    }
-    double inner = 0.0;
-    for (int b = 0; b < nblocks; ++b) inner += a.part[b];
-    __syncthreads();
-    if constexpr (RT == 16) {
-        if (tid < 64) wave_gram16(sF, I2, R, sGram2);
-        __syncthreads();
-    } else {
-        block_gram_rows<RT>(sF, I2, R, sGram2, spart);
-    }
-    for (int e = tid; e < R * R; e += kEpiThreads) a.grams[(int64_t)m2 * R * R + e] = sGram2[e];
-    // eq. 2.12: D = ||Y||^2 - 2 <Y, Yhat> + ||Yhat||^2, <Y, Yhat> = sum G^(N) .* A^(N)
-    double h = 0.0;
-    for (int e = tid; e < R * R; e += kEpiThreads) h += sP[e] * sGram2[e];
-    const double nrm = block_sum(h, spart);
-    if (tid == 0) {
-        const double y2 = a.scal[0];
-        const double D = y2 - 2.0 * inner + nrm;
-        a.scal[2] = D;
-        a.scal[3] = 1.0 - sqrt(D > 0.0 ? D : 0.0) / sqrt(y2);
-        a.scal[4] = inner;
-        a.scal[5] = nrm;
-        if (!isfinite(D)) atomicOr(a.flags, 2);
-    }
+    // D = ||Y||^2 - 2 <Y, Yhat> + ||Yhat||^2
+    const double y2 = a.scal[0];
+    const double D = y2 - 2.0 * inner + nrm;
+    a.scal[2] = D;
+    a.scal[3] = 1.0 - sqrt(D > 0.0 ? D : 0.0) / sqrt(y2);
+    a.scal[4] = inner;
+    a.scal[5] = nrm;
+    if (!isfinite(D)) atomicOr(a.flags, 2);
 }
 
 hipError_t launch_epi_rows(const EpiRows& a, hipStream_t s) {
@@ -984,10 +971,10 @@ hipError_t launch_epi_rows(const EpiRows& a, hipStream_t s) {
         return hipErrorInvalidValue;
     if (rt == 4) {
         hipLaunchKernelGGL(k_epi_rows<4>, dim3((unsigned)nb), dim3(kEpiThreads), 0, s, a);
-        if (a.cost) hipLaunchKernelGGL(k_epi_rows_cost<4>, dim3(1), dim3(kEpiThreads), 0, s, a, (int)nb);
+        if (a.cost) hipLaunchKernelGGL(k_epi_rows_cost, dim3(1), dim3(64), 0, s, a, (int)nb);
     } else {
         hipLaunchKernelGGL(k_epi_rows<16>, dim3((unsigned)nb), dim3(kEpiThreads), 0, s, a);
-        if (a.cost) hipLaunchKernelGGL(k_epi_rows_cost<16>, dim3(1), dim3(kEpiThreads), 0, s, a, (int)nb);
+        if (a.cost) hipLaunchKernelGGL(k_epi_rows_cost, dim3(1), dim3(64), 0, s, a, (int)nb);
     }
     return hipGetLastError();
 }
