@@ -118,14 +118,23 @@ struct MfmaBufs {
     KrGen kg;           // factors for the Khatri-Rao rows
     hipEvent_t ev0;     // if set: recorded at the kernel's start and end (launch-attached timing)
     hipEvent_t ev1;
+    int fac_stage;      // float32 MFMA kernel: LDS floats for staging every factor (fac_stage_floats), 0 = none
 };
+// LDS floats the float32 MFMA contraction uses to stage all factors (each
+// rounded up to 64 floats), or 0 when they exceed kFacStageMax.
+constexpr int64_t kFacStageMax = 8192;
+inline int64_t fac_stage_floats(int N, const int64_t* dims, int R) {
+    int64_t f = 0;
+    for (int m = 0; m < N; ++m) f += (dims[m] * R + 63) / 64 * 64;
+    return f <= kFacStageMax ? f : 0;
+}
 hipError_t launch_contract_mfma(int ydt, int mode, const void* Y, int64_t J, int64_t K, const Tiling& t,
                                 int roles, const MfmaBufs& bufs, hipStream_t stream);
 hipError_t launch_contract_bf16(int ydt, int mode, const void* Y, int64_t J, int64_t K, const Tiling& t,
                                 int roles, const MfmaBufs& bufs, hipStream_t stream);
 bool mfma_supported(int ydt, int fdt, int mode, int R);
 // widest column chunk (a multiple of 32) the float32 / bf16 MFMA kernels hold in LDS
-int64_t mfma_f32_max_cols(int rt, int roles);
+int64_t mfma_f32_max_cols(int rt, int roles, int64_t fac_stage = 0);
 int64_t mfma_bf16_max_cols(int rt, int roles, bool ylo, bool klo);
 
 // One side of the fused partial reduction (float32): output row i of a side is

@@ -102,7 +102,8 @@ static Tiling tile_valu(int64_t J, int64_t K, int R, int fdt, int roles) {
 
 // Tiling of one pass for the MFMA kernel: 256-row blocks, column chunks of
 // whole 32-column steps, about two blocks per compute unit.
-static Tiling tile_mfma(int64_t J, int64_t K, int R, int roles, int kernel, int64_t cols, bool ylo, bool klo) {
+static Tiling tile_mfma(int64_t J, int64_t K, int R, int roles, int kernel, int64_t cols, bool ylo, bool klo,
+                        int64_t fac_stage) {
     Tiling t{};
     t.kernel = kernel;
     t.rt = 16 * (int)cdiv(R, 16);
@@ -114,7 +115,7 @@ static Tiling tile_mfma(int64_t J, int64_t K, int R, int roles, int kernel, int6
     const int64_t target = 256;
     t.ktb = cols > 0 ? cdiv(cols, 32) : std::max<int64_t>(1, cdiv(steps * t.n_jr, target));
     // LDS holds the KR_R rows of a block's steps
-    if (kernel == 2) t.ktb = std::min<int64_t>(t.ktb, mfma_f32_max_cols(t.rt, roles) / 32);
+    if (kernel == 2) t.ktb = std::min<int64_t>(t.ktb, mfma_f32_max_cols(t.rt, roles, fac_stage) / 32);
     if (kernel == 3) t.ktb = std::min<int64_t>(t.ktb, mfma_bf16_max_cols(t.rt, roles, ylo, klo) / 32);
     t.ktb = std::max<int64_t>(1, t.ktb);
     t.n_kc = cdiv(steps, t.ktb);
@@ -134,7 +135,8 @@ static Tiling tile_pass(const cpgrad_plan_s* p, int roles) {
     const int kind = mfma_kind(p);
     if (kind) {
         const bool klo = p->mode == CPG_MODE_BF16_REFINED;
-        return tile_mfma(p->J, p->K, p->R, roles, kind, p->opt_cols, klo && p->ydt == CPG_F32, klo);
+        return tile_mfma(p->J, p->K, p->R, roles, kind, p->opt_cols, klo && p->ydt == CPG_F32, klo,
+                         fac_stage_floats(p->N, p->dims, p->R));
     }
     return tile_valu(p->J, p->K, p->R, p->fdt, roles);
 }
@@ -260,7 +262,8 @@ static hipError_t launch_contract(cpgrad_plan_s* p, const void* Y, const AnyFacS
                                   int roles, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
     if (t.n_kc > 65535) return hipErrorInvalidConfiguration;
     if (t.kernel == 2 || t.kernel == 3) {
-        MfmaBufs o{(float*)p->PRpart, (float*)p->PLpart, p->ld, kr_gen(p, fs.f), ev0, ev1};
+        MfmaBufs o{(float*)p->PRpart, (float*)p->PLpart, p->ld, kr_gen(p, fs.f), ev0, ev1,
+                   (int)fac_stage_floats(p->N, p->dims, p->R)};
         if (t.kernel == 3)
             return launch_contract_bf16(p->ydt, p->mode, Y, p->J, p->K, t, roles, o, p->stream);
         return launch_contract_mfma(p->ydt, p->mode, Y, p->J, p->K, t, roles, o, p->stream);

@@ -26,6 +26,14 @@
 
 #include <hip/hip_ext.h>
 
+// Optional timestamps for profiling builds; compiled out by default.
+#ifndef CPG_CONTRACT_MARK
+#define CPG_CONTRACT_MARK(k)
+#endif
+#ifndef CPG_CONTRACT_WAVE_MARK
+#define CPG_CONTRACT_WAVE_MARK(k)
+#endif
+
 namespace cpg {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -50,14 +58,18 @@ __device__ __forceinline__ void lds_block_sync() {
 template <int NRT, bool DO_R, bool DO_L>
 __global__ __launch_bounds__(256) void k_contract_mfma_f32(const float* __restrict__ Y, int64_t J, int64_t K,
                                                             int64_t kcols, int ld, KrGen kg,
-                                                            float* __restrict__ PRpart, float* __restrict__ PLpart) {
+                                                            float* __restrict__ PRpart, float* __restrict__ PLpart,
+                                                            int fstage) {
     constexpr int RT = NRT * 16;
     constexpr int KRLD = RT + 4;  // LDS row stride of the KR_R tile
-    extern __shared__ float sKRR[];  // kcols x KRLD: KR_R rows of this block's column steps
+    extern __shared__ float sKRR[];  // kcols x KRLD: KR_R rows of this block's column steps, then
+                                     // fstage floats of staged factors
     (void)kcols;                     // sizes sKRR (at least 32 x the block's step count)
     __shared__ float sT[DO_L ? 4 : 1][DO_L ? kStep * kTLd : 1];
     __shared__ v4f sRed[DO_L ? 2 : 1][DO_L ? 4 * 2 * NRT * 64 : 1];
 
+    CPG_CONTRACT_MARK(0);
+    CPG_CONTRACT_WAVE_MARK(50);
     const int tid = threadIdx.x;
     const int w = tid >> 6;
     const int l = tid & 63;
@@ -234,6 +246,86 @@ __global__ __launch_bounds__(256) void k_contract_mfma_f32(const float* __restri
         }
     };
 
+    // The same rows from factors staged in LDS (fstage > 0): every factor is
+    // copied by LDS-DMA loads of 64 floats per wave instruction (each factor's
+    // region rounded up to 64 floats), so the rows need no scattered global
+    // loads.  Mode m's factor sits at the sum of the rounded sizes before it.
+    float* sFac = sKRR + (DO_R ? kcols * KRLD : 0);
+    auto stage_factors = [&]() {
+        int fb = 0;
+        for (int m = 0; m < kg.N; ++m) {
+            const int sz = (int)kg.fd[m].d * R;
+            const int nch = (sz + 63) >> 6;
+            const float* Am = kg.A[m];
+            for (int c = w; c < nch; c += 4) {
+                const int e = min(c * 64 + l, sz - 1);
+                __builtin_amdgcn_global_load_lds((const void*)(Am + e),
+                                                 (__attribute__((address_space(3))) void*)(sFac + fb + c * 64), 4, 0, 0);
+            }
+            fb += nch * 64;
+        }
+    };
+    auto gen_lds = [&](v4f (&t)[kKrBatch], int base, bool with_left) {
+        uint32_t idxL[16], idxR[kKrBatch];
+        int r4[kKrBatch];
+        if (DO_L && with_left) {
+#pragma unroll
+            for (int s = 0; s < 16; ++s) {
+                const int64_t j = jw + 16 * q + s;
+                idxL[s] = j < J ? (uint32_t)j : 0u;
+#pragma unroll
+                for (int rt = 0; rt < NRT; ++rt) krl[rt][s] = j < J ? 1.f : 0.f;
+            }
+        }
+        if (DO_R) {
+#pragma unroll
+            for (int u = 0; u < kKrBatch; ++u) {
+                const int e = base + u * 256 + tid;
+                const int kk = e / (RT / 4);
+                r4[u] = (e - kk * (RT / 4)) * 4;
+                const int64_t k = step_col(kk / kStep) + (kk & (kStep - 1));
+                const bool ok = e < n4 && k < K;
+                idxR[u] = ok ? (uint32_t)k : 0u;
+                const float one = ok ? 1.f : 0.f;
+                t[u] = v4f{one, one, one, one};
+            }
+        }
+        int fb = 0;
+        for (int m = 0; m < kg.N; ++m) {
+            const FastDiv f = kg.fd[m];
+            const float* Fm = sFac + fb;
+            if (DO_L && with_left && m < kg.nstar) {
+#pragma unroll
+                for (int s = 0; s < 16; ++s) {
+                    const uint32_t qd = fast_div(idxL[s], f);
+                    const uint32_t i = idxL[s] - qd * f.d;
+                    idxL[s] = qd;
+#pragma unroll
+                    for (int rt = 0; rt < NRT; ++rt) {
+                        const int r = rt * 16 + c16;
+                        const float x = Fm[i * R + min(r, R - 1)];
+                        krl[rt][s] *= r < R ? x : 0.f;
+                    }
+                }
+            }
+            if (DO_R && m >= kg.nstar) {
+#pragma unroll
+                for (int u = 0; u < kKrBatch; ++u) {
+                    const uint32_t qd = fast_div(idxR[u], f);
+                    const uint32_t i = idxR[u] - qd * f.d;
+                    idxR[u] = qd;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const int r = r4[u] + c;
+                        const float x = Fm[i * R + min(r, R - 1)];
+                        t[u][c] *= r < R ? x : 0.f;
+                    }
+                }
+            }
+            fb += (((int)f.d * R + 63) >> 6) << 6;
+        }
+    };
+
     // Y loads: lane (q, c16), slot c -> rows jw + 4*c16 .. +3 of column
     // step_col(st) + 4c + q, through a buffer resource over the step's 32
     // columns: columns past K, steps past the block's last one and rows past
@@ -261,6 +353,7 @@ __global__ __launch_bounds__(256) void k_contract_mfma_f32(const float* __restri
     // st + kDepth; steps st + 1 .. st + kDepth - 1 are already in flight
     auto step = [&](v4f (&cur)[8], v4f (&nxt)[8], int64_t st) {
         const int buf = (int)(st & 1);
+        CPG_CONTRACT_MARK(2 + 4 * st);
         load_step(nxt, st + kDepth);
         __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the step's MFMAs
         if (DO_R) {
@@ -277,6 +370,7 @@ __global__ __launch_bounds__(256) void k_contract_mfma_f32(const float* __restri
                         accR[e][rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(cur[c][e], b[rt], accR[e][rt], 0, 0, 0);
             }
         }
+        CPG_CONTRACT_MARK(3 + 4 * st);
         if (DO_L) {
             // transpose this wave's 64 x 32 sub-tile through its private LDS region
             float* T = sT[w];
@@ -308,6 +402,7 @@ __global__ __launch_bounds__(256) void k_contract_mfma_f32(const float* __restri
             for (int kt = 0; kt < 2; ++kt)
 #pragma unroll
                 for (int rt = 0; rt < NRT; ++rt) sRed[buf][((w * 2 + kt) * NRT + rt) * 64 + l] = accL[kt][rt];
+            CPG_CONTRACT_MARK(4 + 4 * st);
             lds_block_sync();
             // P_L partial stores of this block row over the step's columns (past K: dropped)
             const int64_t k0 = step_col(st);
@@ -336,6 +431,7 @@ __global__ __launch_bounds__(256) void k_contract_mfma_f32(const float* __restri
                 __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(s0), lrs, (int)off, 0, 0);
                 __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(s1), lrs, (int)(off + (uint32_t)(ld * 4)), 0, 0);
             }
+            CPG_CONTRACT_MARK(5 + 4 * st);
         }
     };
 
@@ -343,7 +439,24 @@ __global__ __launch_bounds__(256) void k_contract_mfma_f32(const float* __restri
     // so the loads of the kDepth steps ahead stay in flight)
     constexpr int NB = kDepth + 1;
     v4f buf[NB][8];
-    {
+    if (fstage > 0) {
+        // staged factors first (their wait must not include Y), then the first
+        // steps of Y, which stay in flight while the rows are formed
+        stage_factors();
+        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): the staging loads
+        CPG_CONTRACT_WAVE_MARK(54);
+        __syncthreads();
+        CPG_CONTRACT_MARK(40);
+#pragma unroll
+        for (int d = 0; d < kDepth; ++d) load_step(buf[d], d);
+        CPG_CONTRACT_MARK(41);
+        v4f krt[kKrBatch];
+        for (int base = 0; base == 0 || (DO_R && base < n4); base += kKrBatch * 256) {
+            gen_lds(krt, base, base == 0);
+            if (DO_R) store_krr(krt, base);
+        }
+        CPG_CONTRACT_MARK(42);
+    } else {
         v4f krt[kKrBatch];
         gen_first(krt, [&] {
 #pragma unroll
@@ -356,12 +469,14 @@ __global__ __launch_bounds__(256) void k_contract_mfma_f32(const float* __restri
         }
     }
     lds_block_sync();
+    CPG_CONTRACT_MARK(1);
     for (int64_t st = 0; st < nsteps; st += NB) {
 #pragma unroll
         for (int ph = 0; ph < NB; ++ph)
             if (ph == 0 || st + ph < nsteps) step(buf[ph], buf[(ph + kDepth) % NB], st + ph);
     }
 
+    CPG_CONTRACT_MARK(60);
     if (DO_R) {
         // lane holds rows jw + 4*(4q + v) + e, rank rt*16 + c16
 #pragma unroll
@@ -387,19 +502,18 @@ bool mfma_supported(int ydt, int fdt, int mode, int R) {
 }
 
 // LDS of one block: static transpose/reduction buffers plus the dynamic KR_R
-// chunk (kcols rows of RT + 4 floats).
+// chunk (kcols rows of RT + 4 floats) and the staged factors.
 static constexpr int64_t static_lds(int nrt, bool do_l) {
     return do_l ? (int64_t)4 * kStep * kTLd * 4 + (int64_t)2 * 4 * 2 * nrt * 64 * 16 : 0;
 }
 constexpr int64_t kLdsPerCu = 160 * 1024;
 
-int64_t mfma_f32_max_cols(int rt, int roles) {
+int64_t mfma_f32_max_cols(int rt, int roles, int64_t fac_stage) {
     const int nrt = rt / 16;
     const int64_t row = (int64_t)(rt + 4) * 4;
-    const int64_t st = static_lds(nrt, (roles & 2) != 0);
-    // two blocks per CU while the rank tile allows it, else one
-    int64_t budget = kLdsPerCu / 2 - st;
-    if (budget < 4 * kStep * row) budget = kLdsPerCu - st;
+    const int64_t st = static_lds(nrt, (roles & 2) != 0) + fac_stage * 4;
+    // one block per CU (the tiling targets one long-running block per CU)
+    const int64_t budget = kLdsPerCu - st;
     return std::max<int64_t>(kStep, (budget / row) / kStep * kStep);
 }
 
@@ -407,7 +521,7 @@ template <int NRT, bool DO_R, bool DO_L>
 static hipError_t launch_one(dim3 grid, const float* Y, int64_t J, int64_t K, int64_t kcols, const MfmaBufs& o,
                              hipStream_t s) {
     auto kern = k_contract_mfma_f32<NRT, DO_R, DO_L>;
-    const size_t dyn = DO_R ? (size_t)kcols * (NRT * 16 + 4) * sizeof(float) : 0;
+    const size_t dyn = (DO_R ? (size_t)kcols * (NRT * 16 + 4) * sizeof(float) : 0) + (size_t)o.fac_stage * 4;
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -417,9 +531,9 @@ static hipError_t launch_one(dim3 grid, const float* Y, int64_t J, int64_t K, in
     }
     if (o.ev0)
         hipExtLaunchKernelGGL(kern, grid, dim3(256), (uint32_t)dyn, s, o.ev0, o.ev1, 0u, Y, J, K, kcols, o.ld, o.kg,
-                              o.PRpart, o.PLpart);
+                              o.PRpart, o.PLpart, o.fac_stage);
     else
-        hipLaunchKernelGGL(kern, grid, dim3(256), dyn, s, Y, J, K, kcols, o.ld, o.kg, o.PRpart, o.PLpart);
+        hipLaunchKernelGGL(kern, grid, dim3(256), dyn, s, Y, J, K, kcols, o.ld, o.kg, o.PRpart, o.PLpart, o.fac_stage);
     return hipGetLastError();
 }
 
@@ -428,7 +542,8 @@ static hipError_t launch_nrt(const float* Y, int64_t J, int64_t K, const Tiling&
                              hipStream_t s) {
     dim3 grid((unsigned)t.n_jr, (unsigned)t.n_kc);
     const int64_t kcols = t.ktb * kStep;
-    if (kcols > mfma_f32_max_cols(NRT * 16, roles)) return hipErrorInvalidValue;
+    if (kcols > mfma_f32_max_cols(NRT * 16, roles, o.fac_stage) || o.fac_stage < 0 || o.fac_stage > kFacStageMax)
+        return hipErrorInvalidValue;
     if (roles == 3) return launch_one<NRT, true, true>(grid, Y, J, K, kcols, o, s);
     if (roles == 1) return launch_one<NRT, true, false>(grid, Y, J, K, kcols, o, s);
     if (roles == 2) return launch_one<NRT, false, true>(grid, Y, J, K, kcols, o, s);
