@@ -44,6 +44,14 @@ __device__ __forceinline__ double block_sum(double v, double* sbuf) {
     return t;
 }
 
+// Stores of split partials that another kernel reads: written through the
+// L2 at system scope (cache policy sc0 sc1), so they stream out while the
+// kernel runs instead of waiting in the L2 for the write-back at its end.
+constexpr int kStoreThrough = 1 | 16;
+__device__ __forceinline__ void store_through(float* p, float v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // Uniform broadcast of lane `src`'s double (src must be wave-uniform).
 __device__ __forceinline__ double readlane_d(double v, int src) {
     const long long b = __double_as_longlong(v);

@@ -398,8 +398,8 @@ __global__ __launch_bounds__(256) void k_contract_bf16(const void* __restrict__ 
                 }
                 const int r = rt * 16 + (lane & 15);
                 const uint32_t off = r < ld ? (uint32_t)(((kt * 16 + 4 * (lane >> 4) + v0) * ld + r) * 4) : kOOB;
-                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(s0), lrs, (int)off, 0, 0);
-                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(s1), lrs, (int)(off + (uint32_t)(ld * 4)), 0, 0);
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(s0), lrs, (int)off, 0, kStoreThrough);
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(s1), lrs, (int)(off + (uint32_t)(ld * 4)), 0, kStoreThrough);
             }
         }
     };
@@ -432,7 +432,7 @@ __global__ __launch_bounds__(256) void k_contract_bf16(const void* __restrict__ 
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
                         const int64_t j = jw + 16 * rr + 4 * q + v;
-                        if (j < J) PRpart[((int64_t)blockIdx.y * J + j) * ld + r] = accR[rr][rt][v];
+                        if (j < J) store_through(&PRpart[((int64_t)blockIdx.y * J + j) * ld + r], accR[rr][rt][v]);
                     }
                 }
             }
