@@ -124,7 +124,8 @@ def _als_setup(dims, R, storage, mode="native", seed=0, snr=25.0):
 @pytest.mark.parametrize("dims,R,storage,ftol", [((20, 20, 20), 3, "f64", 1e-10), ((11, 13, 9, 7), 5, "f64", 1e-10),
                                                  ((20, 30, 40, 50), 16, "f32", 2e-4),
                                                  ((36, 20, 28, 33), 24, "f32", 2e-4),
-                                                 ((5, 6, 3, 4, 2, 3, 5), 10, "f32", 2e-4)])
+                                                 ((5, 6, 3, 4, 2, 3, 5), 10, "f32", 2e-4),
+                                                 ((64, 64, 64, 64), 16, "f32", 2e-4)])
 def test_als_sweep_matches_oracle(dims, R, storage, ftol):
     print(f"[als] dims={dims} R={R} storage={storage}", flush=True)
     P, pr, Y, A, plan = _als_setup(dims, R, storage)
@@ -155,6 +156,22 @@ def test_als_50_sweeps_3d_f64():
     _, fits_ref = O.cp_als(exact_tensor(pr["y"], "f64", pr["dims"]), pr["init"], 50)
     assert np.max(np.abs(np.array(fits) - np.array(fits_ref))) <= 1e-10
     assert fits[-1] > 0.9
+
+
+def test_als_sweeps_f32_track_oracle():
+    """Five float32 sweeps on 20x30x40x50, rank 16 (both passes on the many-block
+    epilogue, Grams carried from sweep to sweep): fits and factors stay with the
+    oracle's float64 sweeps from the same start."""
+    dims, R = (20, 30, 40, 50), 16
+    print(f"[als x5] dims={dims} R={R}", flush=True)
+    P, pr, Y, A, plan = _als_setup(dims, R, "f32")
+    A0 = exact_factors(A)
+    fits = [P.cpals_step(plan, Y, A)[1] for _ in range(5)]
+    A_ref, fits_ref = O.cp_als(exact_tensor(pr["y"], "f32", dims), A0, 5)
+    assert np.max(np.abs(np.array(fits) - np.array(fits_ref))) <= 1e-4, (fits, fits_ref)
+    A_gpu = exact_factors(A)
+    for n in range(len(dims)):
+        assert rel_fro(A_gpu[n], A_ref[n]) <= 1e-3, (n, rel_fro(A_gpu[n], A_ref[n]))
 
 
 @pytest.mark.parametrize("dims,R,storage", [((20, 20, 20), 3, "f64"), ((20, 30, 40, 50), 16, "f32"),
