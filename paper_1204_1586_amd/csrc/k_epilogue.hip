@@ -477,10 +477,18 @@ __device__ __forceinline__ bool wave_eliminate(int R, int64_t I, const double* s
 __device__ __forceinline__ void wave_gram16(const double* sF, int64_t I, int R, double* gout) {
     const int l = threadIdx.x & 63;
     v4d acc = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t i0 = 0; i0 < I; i0 += 4) {
-        const int64_t i = i0 + (l >> 4);
-        const double v = i < I ? sF[i * 16 + (l & 15)] : 0.0;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v, v, acc, 0, 0, 0);
+    // four blocks per round: their LDS reads go out together, then the
+    // products run in row order
+    for (int64_t i0 = 0; i0 < I; i0 += 16) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t i = i0 + 4 * u + (l >> 4);
+            const double x = sF[min(i, I - 1) * 16 + (l & 15)];
+            v[u] = i < I ? x : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v[u], v[u], acc, 0, 0, 0);
     }
     // output of the float64 16x16x4 product: lane l, item j holds D[(l >> 4) + 4 j][l & 15]
     const int c = l & 15;
@@ -814,17 +822,43 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_rows(EpiRows a) {
         }
     };
 
-    // first mode: G^(n1), the Grams (one round of loads), then the solve (one jittered retry)
-    for (int64_t o = tid; o < I1 * R; o += kEpiThreads) {
-        const int64_t i = o / R;
-        sG[i * RT + (o - i * R)] = (double)a.Gpre[o];
-    }
-    for (int e = tid; e < R * R; e += kEpiThreads) {
-        double v = 1.0;
-        for (int k = 0; k < N; ++k)
-            if (k != m1 && k != m2) v *= a.grams[(int64_t)k * R * R + e];
-        sP[e] = v;
-        sGram2[e] = a.grams[(int64_t)m2 * R * R + e];   // Gram of A^(n2) before its update
+    // first mode: G^(n1) and the Grams in one round of loads, then the solve
+    // (one jittered retry)
+    {
+        constexpr int kGPer = kEpiGCap / kEpiThreads;   // I1 * R <= kEpiGCap
+        static_assert(RT * RT <= kEpiThreads, "one Gram entry per thread");
+        const int64_t nG = I1 * R;
+        // loads without branches (clamped indices, values selected after),
+        // so they all go out before the first wait
+        float gp[kGPer];
+#pragma unroll
+        for (int u = 0; u < kGPer; ++u) {
+            const int64_t o = tid + (int64_t)u * kEpiThreads;
+            gp[u] = a.Gpre[min(o, nG - 1)];
+        }
+        const bool has_e = tid < R * R;
+        const int e_c = min(tid, R * R - 1);
+        double gv[CPG_MAX_MODES];
+#pragma unroll
+        for (int k = 0; k < CPG_MAX_MODES; ++k) gv[k] = a.grams[(int64_t)min(k, N - 1) * R * R + e_c];
+#pragma unroll
+        for (int u = 0; u < kGPer; ++u) {
+            const int64_t o = tid + (int64_t)u * kEpiThreads;
+            if (o < nG) {
+                const int64_t i = o / R;
+                sG[i * RT + (o - i * R)] = (double)gp[u];
+            }
+        }
+        if (has_e) {
+            double v = 1.0, g2 = 0.0;
+#pragma unroll
+            for (int k = 0; k < CPG_MAX_MODES; ++k) {
+                if (k < N && k != m1 && k != m2) v *= gv[k];
+                if (k == m2) g2 = gv[k];
+            }
+            sP[tid] = v;
+            sGram2[tid] = g2;   // Gram of A^(n2) before its update
+        }
     }
     form_gamma(sGram2, false);
     bool ok1 = wave_eliminate<float, RT>(R, I1, sG, sGam, blockIdx.x == 0 ? A1 : nullptr, sF, &sFlag);
@@ -923,18 +957,36 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_rows(EpiRows a) {
             }
             __syncthreads();
         }
+        // one (row, rank) entry per thread (nrows * RT <= kEpiRowsCells <= kEpiThreads)
         double acc = 0.0, quad = 0.0;
-        for (int e = tid; e < nrows * R; e += kEpiThreads) {
-            const int il = e / R, r = e - (e / R) * R;
+        if (tid < nrows * R) {
+            const int il = tid / R, r = tid - (tid / R) * R;
             const double ar = sA2[il * RT + r];
-            acc += sX[il * RT + r] * ar;
+            acc = sX[il * RT + r] * ar;
             double t = 0.0;
-            for (int c = 0; c < R; ++c) t += sP[r * R + c] * sGram1[r * R + c] * sA2[il * RT + c];
-            quad += ar * t;
+#pragma unroll
+            for (int c = 0; c < RT; ++c)
+                if (c < R) t += sP[r * R + c] * sGram1[r * R + c] * sA2[il * RT + c];
+            quad = ar * t;
         }
-        const double inner = block_sum(acc, spart);
-        const double h = block_sum(quad, spart);
+        // fixed-order sums: a butterfly in each wave (every lane ends with the
+        // same value), then the waves in order
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            acc += __shfl_xor(acc, o);
+            quad += __shfl_xor(quad, o);
+        }
+        if ((tid & 63) == 0) {
+            spart[2 * (tid >> 6)] = acc;
+            spart[2 * (tid >> 6) + 1] = quad;
+        }
+        __syncthreads();
         if (tid == 0) {
+            double inner = 0.0, h = 0.0;
+            for (int w = 0; w < kEpiThreads / 64; ++w) {
+                inner += spart[2 * w];
+                h += spart[2 * w + 1];
+            }
             a.part[2 * blockIdx.x] = inner;
             a.part[2 * blockIdx.x + 1] = h;
         }
