@@ -426,11 +426,21 @@ __device__ __forceinline__ bool wave_eliminate(int R, int64_t I, const double* s
 #pragma unroll
         for (int k = 0; k < RT; ++k) {
             if (k < R && ok) {
+                // the pivot and its reciprocal estimate first, then all the
+                // step's multipliers Gamma'_sk (uniform, in scalar registers),
+                // so their latencies overlap instead of stalling each update
                 const double piv = readlane_d(gc[k], k);
+                double rp = __builtin_amdgcn_rcp(piv);
+                __builtin_amdgcn_sched_barrier(0);
+                double mk[RT];
+#pragma unroll
+                for (int s = 0; s < RT; ++s) mk[s] = s == k ? 0.0 : readlane_d(gc[s], k);
+                __builtin_amdgcn_sched_barrier(0);
                 if (!(piv > 0.0) || !isfinite(piv)) {
                     ok = false;
                 } else {
-                    const double rp = rcp_d(piv);
+                    rp = __builtin_fma(rp, __builtin_fma(-piv, rp, 1.0), rp);   // two Newton steps
+                    rp = __builtin_fma(rp, __builtin_fma(-piv, rp, 1.0), rp);
                     const double tg = gc[k] * rp;
                     double tx[kSets];
 #pragma unroll
@@ -438,10 +448,9 @@ __device__ __forceinline__ bool wave_eliminate(int R, int64_t I, const double* s
 #pragma unroll
                     for (int s = 0; s < RT; ++s) {
                         if (s == k) continue;
-                        const double m = readlane_d(gc[s], k);   // Gamma'_sk
-                        gc[s] -= m * tg;
+                        gc[s] -= mk[s] * tg;
 #pragma unroll
-                        for (int q = 0; q < kSets; ++q) xc[q][s] -= m * tx[q];
+                        for (int q = 0; q < kSets; ++q) xc[q][s] -= mk[s] * tx[q];
                     }
                     gc[k] = tg;
 #pragma unroll
