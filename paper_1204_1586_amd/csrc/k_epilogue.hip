@@ -425,37 +425,37 @@ __device__ __forceinline__ bool wave_eliminate(int R, int64_t I, const double* s
         bool ok = true;
 #pragma unroll
         for (int k = 0; k < RT; ++k) {
-            if (k < R && ok) {
+            if (k < R) {
                 // the pivot and its reciprocal estimate first, then all the
                 // step's multipliers Gamma'_sk (uniform, in scalar registers),
-                // so their latencies overlap instead of stalling each update
+                // so their latencies overlap instead of stalling each update.
+                // No branch on the pivot: after a bad one the remaining steps
+                // run on values that are discarded (ok false)
                 const double piv = readlane_d(gc[k], k);
+                ok = ok && piv > 0.0 && isfinite(piv);
                 double rp = __builtin_amdgcn_rcp(piv);
                 __builtin_amdgcn_sched_barrier(0);
                 double mk[RT];
 #pragma unroll
                 for (int s = 0; s < RT; ++s) mk[s] = s == k ? 0.0 : readlane_d(gc[s], k);
                 __builtin_amdgcn_sched_barrier(0);
-                if (!(piv > 0.0) || !isfinite(piv)) {
-                    ok = false;
-                } else {
-                    rp = __builtin_fma(rp, __builtin_fma(-piv, rp, 1.0), rp);   // two Newton steps
-                    rp = __builtin_fma(rp, __builtin_fma(-piv, rp, 1.0), rp);
-                    const double tg = gc[k] * rp;
-                    double tx[kSets];
+                rp = __builtin_fma(rp, __builtin_fma(-piv, rp, 1.0), rp);   // two Newton steps
+                rp = __builtin_fma(rp, __builtin_fma(-piv, rp, 1.0), rp);
+                const double tg = gc[k] * rp;
+                double tx[kSets];
 #pragma unroll
-                    for (int q = 0; q < kSets; ++q) tx[q] = xc[q][k] * rp;
+                for (int q = 0; q < kSets; ++q) tx[q] = xc[q][k] * rp;
+                // row k + 1 first: the next step's pivot is ready early
 #pragma unroll
-                    for (int s = 0; s < RT; ++s) {
-                        if (s == k) continue;
-                        gc[s] -= mk[s] * tg;
+                for (int d = 1; d < RT; ++d) {
+                    const int s = (k + d) % RT;
+                    gc[s] -= mk[s] * tg;
 #pragma unroll
-                        for (int q = 0; q < kSets; ++q) xc[q][s] -= mk[s] * tx[q];
-                    }
-                    gc[k] = tg;
-#pragma unroll
-                    for (int q = 0; q < kSets; ++q) xc[q][k] = tx[q];
+                    for (int q = 0; q < kSets; ++q) xc[q][s] -= mk[s] * tx[q];
                 }
+                gc[k] = tg;
+#pragma unroll
+                for (int q = 0; q < kSets; ++q) xc[q][k] = tx[q];
             }
         }
         if (ok) {
