@@ -1007,14 +1007,19 @@ __global__ __launch_bounds__(kEpiThreads) void k_epi_rows(EpiRows a) {
 // the cost of eq. 2.12 and the fit from the per-block partials (block order).
 // The Gram of the new A^(n2) is left to the next pass's reduction.
 __global__ void k_epi_rows_cost(EpiRows a, int nblocks) {
-    if (threadIdx.x != 0) return;
-    double inner = 0.0, nrm = 0.0;
-    for (int b = 0; b < nblocks; ++b) {
-        inner += a.part[2 * b];
-        nrm += a.part[2 * b + 1];
-    }
-    // D = ||Y||^2 - 2 <Y, Yhat> + ||Yhat||^2
+    // lane b loads block b's pair (all loads in flight at once); lane 0 adds
+    // them in block order
+    const int l = threadIdx.x;
+    const int b = min(l, nblocks - 1);
+    const double pi = a.part[2 * b], pn = a.part[2 * b + 1];
     const double y2 = a.scal[0];
+    double inner = 0.0, nrm = 0.0;
+    for (int k = 0; k < nblocks; ++k) {
+        inner += readlane_d(pi, k);
+        nrm += readlane_d(pn, k);
+    }
+    if (l != 0) return;
+    // D = ||Y||^2 - 2 <Y, Yhat> + ||Yhat||^2
     const double D = y2 - 2.0 * inner + nrm;
     a.scal[2] = D;
     a.scal[3] = 1.0 - sqrt(D > 0.0 ? D : 0.0) / sqrt(y2);
