@@ -186,8 +186,13 @@ def test_cp_fit_matches_explicit_residual(dims, R, storage):
     assert abs(fit - O.fit_from_cost(D, O.norm2(Yx))) <= tol * 10
 
 
-def test_not_spd_is_reported_and_factor_kept():
-    P, pr, Y, A, plan = _als_setup((8, 9, 10), 3, "f64")
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_not_spd_is_reported_and_factor_kept(storage):
+    """Zero factors make every Gamma zero: the solve fails, also after the
+    jittered retry; the status says so and the factors are kept (float64
+    and float32 take different epilogue kernels)."""
+    print(f"[not spd] storage={storage}", flush=True)
+    P, pr, Y, A, plan = _als_setup((8, 9, 10), 3, storage)
     for M in A:
         M.zero_()
     before = exact_factors(A)
