@@ -125,7 +125,9 @@ def _als_setup(dims, R, storage, mode="native", seed=0, snr=25.0):
                                                  ((20, 30, 40, 50), 16, "f32", 2e-4),
                                                  ((36, 20, 28, 33), 24, "f32", 2e-4),
                                                  ((5, 6, 3, 4, 2, 3, 5), 10, "f32", 2e-4),
-                                                 ((64, 64, 64, 64), 16, "f32", 2e-4)])
+                                                 ((64, 64, 64, 64), 16, "f32", 2e-4),
+                                                 ((8, 9, 10), 3, "f32", 2e-4),
+                                                 ((12, 10, 14, 9), 7, "f32", 2e-4)])
 def test_als_sweep_matches_oracle(dims, R, storage, ftol):
     print(f"[als] dims={dims} R={R} storage={storage}", flush=True)
     P, pr, Y, A, plan = _als_setup(dims, R, storage)
