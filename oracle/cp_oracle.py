@@ -14,7 +14,7 @@ import numpy as np
 import scipy.linalg
 
 __all__ = [
-    "as_tensor", "ivec", "unfold", "unfold_rc", "reshape_view", "khatri_rao", "kr_except",
+    "as_tensor", "ivec", "unfold", "unfold_rc", "khatri_rao", "kr_except",
     "mttkrp", "cp_gradient_all", "gradient_entry", "n_star", "gram", "gamma",
     "cholesky_jitter_solve", "NotSPD", "als_order", "als_sweep", "cp_als", "cp_full",
     "cost_explicit", "cost_identity", "fit_from_cost", "norm2", "e_gradient_all",
@@ -44,11 +44,6 @@ def ivec(idx, dims):
         lin += int(i) * stride
         stride *= int(I)
     return lin
-
-
-def reshape_view(Y, shape):
-    """Def. 2.1, eq. 2.2: same vec(Y), new shape (column-major)."""
-    return np.reshape(np.reshape(Y, -1, order="F"), tuple(shape), order="F")
 
 
 def unfold_rc(Y, rows, cols):
