@@ -73,7 +73,9 @@ typedef enum {
     CPG_ERR_NOT_SPD = -4,      /* eq. 2.14 matrix not positive definite after one
                                   jittered retry; that mode's factor is left as it was */
     CPG_ERR_UNSUPPORTED = -5,  /* valid but unsupported combination                   */
-    CPG_ERR_NONFINITE = -6     /* the cost came out NaN or infinite                   */
+    CPG_ERR_NONFINITE = -6,    /* the cost came out NaN or infinite                   */
+    CPG_ERR_SCRATCH = -7       /* cpgrad_all_modes_noalloc: the shape needs more
+                                  workspace than the static scratch array holds       */
 } cpg_status;
 
 /* Plan options (cpgrad_set_option). */
@@ -157,6 +159,28 @@ int cp_fit(cpgrad_plan_t p, const void* Y, const void* const* A,
 /* Wait for the plan's stream and return the cost and fit of the last
  * cpals_step / cp_fit, with its status (CPG_ERR_NOT_SPD / CPG_ERR_NONFINITE). */
 int cpgrad_last_fit(cpgrad_plan_t p, double* cost_out, double* fit_out);
+
+/* Allocation-free variant of cpgrad_all_modes, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  No plan is created: the shape, types and
+ * stream are passed directly (same meaning and checks as cpgrad_plan), and
+ * every intermediate (split partials, chain buffers) lives in one static
+ * device array of CPG_NOALLOC_SCRATCH_BYTES bytes that the library holds on
+ * each GPU it runs on until the process ends.  The call performs no
+ * hipMalloc / hipFree / hipMemset and no host allocation; it enqueues the
+ * same kernels as cpgrad_all_modes on `stream` and returns without waiting.
+ * Y, A (host array of N device pointers) and G are as for cpgrad_all_modes;
+ * the HIP device current on the calling thread must be the stream's device.
+ * The scratch array is shared by every call on that GPU and keeps the last
+ * call's contents: calls that overlap on one GPU (other streams, other host
+ * threads) race and must be serialised by the caller.
+ * Errors: CPG_ERR_INVALID / CPG_ERR_UNSUPPORTED as cpgrad_plan and
+ * cpgrad_all_modes; CPG_ERR_SCRATCH if the shape needs more workspace than
+ * the array holds (cpgrad_plan_info's workspace_bytes of an equal plan tells
+ * what a shape needs); CPG_ERR_HIP. */
+#define CPG_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+int cpgrad_all_modes_noalloc(int N, const int64_t* dims, int R, int y_dtype, int factor_dtype, int mode,
+                             const void* Y, const void* const* A, void* const* G, void* stream);
 
 /* Release the plan's workspace.  NULL is accepted. */
 int cpgrad_destroy(cpgrad_plan_t p);

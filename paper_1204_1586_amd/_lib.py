@@ -21,7 +21,8 @@ CPG_OPT_FORCE_NSTAR, CPG_OPT_KERNEL, CPG_OPT_PROFILE, CPG_OPT_MFMA_COLS = 1, 2, 
 MAX_MODES, MAX_RANK = 16, 64
 
 STATUS = {0: "CPG_OK", -1: "CPG_ERR_INVALID", -2: "CPG_ERR_NOMEM", -3: "CPG_ERR_HIP", -4: "CPG_ERR_NOT_SPD",
-          -5: "CPG_ERR_UNSUPPORTED", -6: "CPG_ERR_NONFINITE"}
+          -5: "CPG_ERR_UNSUPPORTED", -6: "CPG_ERR_NONFINITE", -7: "CPG_ERR_SCRATCH"}
+NOALLOC_SCRATCH_BYTES = 32 << 20
 
 DTYPES = {"f64": CPG_F64, "f32": CPG_F32, "bf16": CPG_BF16}
 MODES = {"native": CPG_MODE_NATIVE, "bf16": CPG_MODE_BF16, "bf16_refined": CPG_MODE_BF16_REFINED}
@@ -32,7 +33,7 @@ EXPORTS = ["cpgrad_plan", "cpgrad_plan_info", "cpgrad_query", "cpgrad_set_option
            "cpgrad_status_string", "cpgrad_version",
            "cpmlp_create", "cpmlp_num_params", "cpmlp_set_params", "cpmlp_get_params", "cpmlp_forward",
            "cpmlp_gradients", "cpmlp_train_step", "cpmlp_destroy", "cpals_features", "cp_fit_extrapolated",
-           "cpals_learned_step"]
+           "cpals_learned_step", "cpgrad_all_modes_noalloc"]
 NFEAT = 12
 
 
@@ -59,6 +60,8 @@ def _load():
         "cpgrad_profile_read": (ctypes.c_int, [vp, ctypes.c_int, dp, ctypes.POINTER(ctypes.c_int64)]),
         "cpgrad_bind": (ctypes.c_int, [vp, vp]),
         "cpgrad_all_modes": (ctypes.c_int, [vp, vp, ctypes.POINTER(vp), ctypes.POINTER(vp)]),
+        "cpgrad_all_modes_noalloc": (ctypes.c_int, [ctypes.c_int, i64p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                     ctypes.c_int, vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]),
         "cpals_step": (ctypes.c_int, [vp, vp, ctypes.POINTER(vp), dp, dp]),
         "cp_fit": (ctypes.c_int, [vp, vp, ctypes.POINTER(vp), dp, dp]),
         "cpgrad_last_fit": (ctypes.c_int, [vp, dp, dp]),
@@ -230,6 +233,27 @@ def cpgrad_all_modes(plan, Y, A, G):
         _check_factors(plan, G, "G")
     y, a, g = _marshal(plan, "all_modes", Y, (A, G), checks)
     _check(LIB.cpgrad_all_modes(plan.handle, y, a, g), "cpgrad_all_modes")
+
+
+def cpgrad_all_modes_noalloc(dims, R, Y, A, G, y_dtype="f32", factor_dtype=None, mode="native", stream=None):
+    """cpgrad_all_modes without a plan: every intermediate lives in the library's
+    static device scratch array (no device allocation; asynchronous)."""
+    ydt = DTYPES[y_dtype] if isinstance(y_dtype, str) else int(y_dtype)
+    if factor_dtype is None:
+        factor_dtype = "f64" if ydt == CPG_F64 else "f32"
+    fdt = DTYPES[factor_dtype] if isinstance(factor_dtype, str) else int(factor_dtype)
+    md = MODES[mode] if isinstance(mode, str) else int(mode)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    shape = Plan(None, dims, R, ydt, fdt, md, stream)   # argument checks only (owns no library plan)
+    _check_y(shape, Y)
+    _check_factors(shape, A)
+    _check_factors(shape, G, "G")
+    dims = [int(d) for d in dims]
+    arr = (ctypes.c_int64 * len(dims))(*dims)
+    _check(LIB.cpgrad_all_modes_noalloc(len(dims), arr, int(R), ydt, fdt, md, ctypes.c_void_p(Y.data_ptr()),
+                                        _ptrs(A), _ptrs(G), ctypes.c_void_p(stream.cuda_stream)),
+           "cpgrad_all_modes_noalloc")
 
 
 def cpals_step(plan, Y, A, sync=True):

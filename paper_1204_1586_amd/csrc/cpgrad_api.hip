@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -31,6 +32,7 @@ struct cpgrad_plan_s {
     // device workspace
     char* ws = nullptr;
     size_t ws_bytes = 0;
+    bool ws_external = false;              // ws is the library's static scratch array (never freed or grown)
     void* PR = nullptr;
     void* PL = nullptr;
     void* chain[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -144,7 +146,7 @@ static Tiling tile_pass(const cpgrad_plan_s* p, int roles) {
 static int hip_status(hipError_t e) { return e == hipSuccess ? CPG_OK : CPG_ERR_HIP; }
 
 static void release(cpgrad_plan_s* p) {
-    if (p->ws) (void)hipFree(p->ws);
+    if (p->ws && !p->ws_external) (void)hipFree(p->ws);
     p->ws = nullptr;
     p->ws_bytes = 0;
 }
@@ -187,6 +189,7 @@ static int configure(cpgrad_plan_s* p) {
     const size_t oF = off;      off += al(16 * sizeof(int));
     const size_t oRp = off;     off += al(2 * kEpiRowsMaxBlocks * 8);
     if (off > p->ws_bytes) {
+        if (p->ws_external) return CPG_ERR_SCRATCH;
         release(p);
         void* mem = nullptr;
         if (hipMalloc(&mem, off) != hipSuccess) {
@@ -212,9 +215,10 @@ static int configure(cpgrad_plan_s* p) {
     p->flags = (int*)(b + oF);
     p->rpart = (double*)(b + oRp);
 
+    p->bound = nullptr;
+    if (p->ws_external) return CPG_OK;   // the all-mode gradient reads neither scal nor flags
     if (hipMemsetAsync(p->scal, 0, 16 * 8, p->stream) != hipSuccess) return CPG_ERR_HIP;
     if (hipMemsetAsync(p->flags, 0, 16 * sizeof(int), p->stream) != hipSuccess) return CPG_ERR_HIP;
-    p->bound = nullptr;
     return CPG_OK;
 }
 
@@ -773,27 +777,10 @@ static AnyFacSet plan_facset(const cpgrad_plan_s* p, void* base) {
     return facsets(p, ptrs);
 }
 
-extern "C" {
-
-const char* cpgrad_version(void) { return "cpgrad 0.1 (gfx950)"; }
-
-const char* cpgrad_status_string(int s) {
-    switch (s) {
-        case CPG_OK: return "CPG_OK";
-        case CPG_ERR_INVALID: return "CPG_ERR_INVALID: invalid argument";
-        case CPG_ERR_NOMEM: return "CPG_ERR_NOMEM: device allocation failed";
-        case CPG_ERR_HIP: return "CPG_ERR_HIP: HIP runtime error";
-        case CPG_ERR_NOT_SPD: return "CPG_ERR_NOT_SPD: normal equations not positive definite";
-        case CPG_ERR_UNSUPPORTED: return "CPG_ERR_UNSUPPORTED: unsupported type/mode combination";
-        case CPG_ERR_NONFINITE: return "CPG_ERR_NONFINITE: non-finite cost";
-        default: return "unknown cpgrad status";
-    }
-}
-
-int cpgrad_plan(cpgrad_plan_t* out, int N, const int64_t* dims, int R, int y_dtype, int factor_dtype, int mode,
-                void* stream) {
-    if (!out || !dims) return CPG_ERR_INVALID;
-    *out = nullptr;
+// Shape, types and split of a plan (no device work, no allocation).
+static int plan_init(cpgrad_plan_s* p, int N, const int64_t* dims, int R, int y_dtype, int factor_dtype, int mode,
+                     void* stream) {
+    if (!dims) return CPG_ERR_INVALID;
     {
         const int st = check_shape(N, dims, R);
         if (st) return st;
@@ -809,9 +796,6 @@ int cpgrad_plan(cpgrad_plan_t* out, int N, const int64_t* dims, int R, int y_dty
     const bool b16 = (y_dtype == CPG_BF16 && factor_dtype == CPG_F32 && mode != CPG_MODE_NATIVE);
     if (!(f64 || f32 || b16)) return CPG_ERR_UNSUPPORTED;
     if (factor_dtype == CPG_BF16) return CPG_ERR_UNSUPPORTED;
-
-    cpgrad_plan_s* p = new (std::nothrow) cpgrad_plan_s();
-    if (!p) return CPG_ERR_NOMEM;
     p->N = N;
     p->R = R;
     p->ld = 4 * ((R + 3) / 4);
@@ -828,13 +812,91 @@ int cpgrad_plan(cpgrad_plan_t* out, int N, const int64_t* dims, int R, int y_dty
     for (int n = N - 1; n >= 0; --n) p->Kn[n] = p->Kn[n + 1] * dims[n];
     // Algorithm 2, step 1: n* = max{n : J_n <= K_n}, n in [1, N-1]; 1 if none
     p->nstar_auto = default_nstar(N, dims);
+    return CPG_OK;
+}
+
+// Enqueue the all-mode gradient on a configured plan.
+static int all_modes_core(cpgrad_plan_s* p, const void* Y, const void* const* A, void* const* G) {
+    const AnyFacSet fs = facsets(p, A);
+    CPG_TRY(run_contract(p, Y, fs, p->t_fused, 3));
+    bool pre = false;
+    const bool tail = p->fdt == CPG_F32 && epilogue_fits(p);
+    int st = finish_partials(p, p->fdt == CPG_F32 ? &fs.f : nullptr, p->t_fused, 3, G[p->nstar - 1], G[p->nstar],
+                             false, &pre, tail ? G : nullptr);
+    if (st) return st;
+    if (epilogue_fits(p)) {
+        if (p->fdt == CPG_F64) return run_both_sides<double>(p, fs.d, (void* const*)A, G);
+        if (pre) return all_modes_tail(p, fs.f, G);
+        return run_both_sides<float>(p, fs.f, (void* const*)A, G);
+    }
+    st = right_chain(p, fs, (void* const*)A, G, false);
+    if (st) return st;
+    return left_chain(p, fs, (void* const*)A, G, false);
+}
+
+// Static scratch of the allocation-free entry point: one copy per GPU, held
+// until the process ends.  Host code never uses the array's name as an
+// address: its device address is looked up once per device (with that device
+// current) and kept in scratch_dev[].
+static __device__ __align__(256) char scratch[CPG_NOALLOC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+static void* scratch_dev[kMaxDevices];
+static std::mutex scratch_mu;
+
+static int scratch_ptr(void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return CPG_ERR_HIP;
+    if (dev < 0 || dev >= kMaxDevices) return CPG_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_dev[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return CPG_ERR_HIP;
+        }
+        scratch_dev[dev] = ptr;
+    }
+    *out = scratch_dev[dev];
+    return CPG_OK;
+}
+
+extern "C" {
+
+const char* cpgrad_version(void) { return "cpgrad 0.1 (gfx950)"; }
+
+const char* cpgrad_status_string(int s) {
+    switch (s) {
+        case CPG_OK: return "CPG_OK";
+        case CPG_ERR_INVALID: return "CPG_ERR_INVALID: invalid argument";
+        case CPG_ERR_NOMEM: return "CPG_ERR_NOMEM: device allocation failed";
+        case CPG_ERR_HIP: return "CPG_ERR_HIP: HIP runtime error";
+        case CPG_ERR_NOT_SPD: return "CPG_ERR_NOT_SPD: normal equations not positive definite";
+        case CPG_ERR_UNSUPPORTED: return "CPG_ERR_UNSUPPORTED: unsupported type/mode combination";
+        case CPG_ERR_NONFINITE: return "CPG_ERR_NONFINITE: non-finite cost";
+        case CPG_ERR_SCRATCH:
+            return "CPG_ERR_SCRATCH: the shape needs more workspace than the static scratch array holds";
+        default: return "unknown cpgrad status";
+    }
+}
+
+int cpgrad_plan(cpgrad_plan_t* out, int N, const int64_t* dims, int R, int y_dtype, int factor_dtype, int mode,
+                void* stream) {
+    if (!out) return CPG_ERR_INVALID;
+    *out = nullptr;
+    cpgrad_plan_s* p = new (std::nothrow) cpgrad_plan_s();
+    if (!p) return CPG_ERR_NOMEM;
+    int st = plan_init(p, N, dims, R, y_dtype, factor_dtype, mode, stream);
+    if (st) {
+        delete p;
+        return st;
+    }
     void* h = nullptr;
     if (hipHostMalloc(&h, 16 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
         delete p;
         return CPG_ERR_NOMEM;
     }
     p->host = (double*)h;
-    const int st = configure(p);
+    st = configure(p);
     if (st != CPG_OK) {
         release(p);
         (void)hipHostFree(p->host);
@@ -923,21 +985,27 @@ int cpgrad_all_modes(cpgrad_plan_t p, const void* Y, const void* const* A, void*
     if (((uintptr_t)Y & 15) != 0) return CPG_ERR_INVALID;
     for (int n = 0; n < p->N; ++n)
         if (!A[n] || !G[n]) return CPG_ERR_INVALID;
-    const AnyFacSet fs = facsets(p, A);
-    CPG_TRY(run_contract(p, Y, fs, p->t_fused, 3));
-    bool pre = false;
-    const bool tail = p->fdt == CPG_F32 && epilogue_fits(p);
-    int st = finish_partials(p, p->fdt == CPG_F32 ? &fs.f : nullptr, p->t_fused, 3, G[p->nstar - 1], G[p->nstar],
-                             false, &pre, tail ? G : nullptr);
+    return all_modes_core(p, Y, A, G);
+}
+
+int cpgrad_all_modes_noalloc(int N, const int64_t* dims, int R, int y_dtype, int factor_dtype, int mode,
+                             const void* Y, const void* const* A, void* const* G, void* stream) {
+    if (!Y || !A || !G) return CPG_ERR_INVALID;
+    if (((uintptr_t)Y & 15) != 0) return CPG_ERR_INVALID;
+    cpgrad_plan_s p;   // on the stack: its vectors stay empty (no profiling), nothing is allocated
+    int st = plan_init(&p, N, dims, R, y_dtype, factor_dtype, mode, stream);
     if (st) return st;
-    if (epilogue_fits(p)) {
-        if (p->fdt == CPG_F64) return run_both_sides<double>(p, fs.d, (void* const*)A, G);
-        if (pre) return all_modes_tail(p, fs.f, G);
-        return run_both_sides<float>(p, fs.f, (void* const*)A, G);
-    }
-    st = right_chain(p, fs, (void* const*)A, G, false);
+    for (int n = 0; n < N; ++n)
+        if (!A[n] || !G[n]) return CPG_ERR_INVALID;
+    void* ws = nullptr;
+    st = scratch_ptr(&ws);
     if (st) return st;
-    return left_chain(p, fs, (void* const*)A, G, false);
+    p.ws = (char*)ws;
+    p.ws_bytes = CPG_NOALLOC_SCRATCH_BYTES;
+    p.ws_external = true;
+    st = configure(&p);
+    if (st) return st;
+    return all_modes_core(&p, Y, A, G);
 }
 
 int cpals_step(cpgrad_plan_t p, const void* Y, void* const* A, double* cost_out, double* fit_out) {

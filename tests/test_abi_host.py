@@ -104,3 +104,19 @@ def test_query_flops(dims, R):
     assert q["alg_flops"] == _tally(dims, R, O.n_star(dims))
     # the O(R prod I_n) claim (Section 1, Table 4.1): at most a few % above 4 R J_N
     assert q["alg_flops"] <= 4 * R * np.prod(dims) * 1.2
+
+
+def test_noalloc_rejects_bad_arguments_before_any_device_call():
+    dims = (ctypes.c_int64 * 3)(4, 5, 6)
+    vp = ctypes.c_void_p
+    ptrs = (vp * 3)(16, 32, 48)
+    f = P.LIB.cpgrad_all_modes_noalloc
+    assert f(3, dims, 3, 1, 1, 0, None, ptrs, ptrs, None) == -1                 # NULL Y
+    assert f(3, dims, 3, 1, 1, 0, vp(16), None, ptrs, None) == -1               # NULL A
+    assert f(3, dims, 3, 1, 1, 0, vp(17), ptrs, ptrs, None) == -1               # misaligned Y
+    assert f(1, dims, 3, 1, 1, 0, vp(16), ptrs, ptrs, None) == -1               # N < 2
+    assert f(3, dims, 0, 1, 1, 0, vp(16), ptrs, ptrs, None) == -1               # R < 1
+    assert f(3, dims, 3, 0, 1, 0, vp(16), ptrs, ptrs, None) == -5               # f64 tensor, f32 factors
+    nulls = (vp * 3)(16, None, 48)
+    assert f(3, dims, 3, 1, 1, 0, vp(16), nulls, ptrs, None) == -1             # a NULL factor
+    assert P.LIB.cpgrad_status_string(-7).decode().startswith("CPG_ERR_SCRATCH")
