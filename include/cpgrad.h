@@ -36,6 +36,12 @@
  *   BF16     F32           BF16_REFINED    + Y*KR_lo term (Y is exact in bf16)
  *   Gram matrices, the normal-equation solve of eq. 2.14, ||Y||^2 and the
  *   cost of eq. 2.12 are float64 in every mode.
+ *   The reduced-precision modes run only on the matrix cores: a plan whose
+ *   shape they cannot take (J = I_1...I_n* not a multiple of 8, or beyond the
+ *   kernels' 32-bit index and grid limits) is refused with
+ *   CPG_ERR_UNSUPPORTED instead of silently running in full precision.  The
+ *   native float32 form falls back to the vector-ALU kernel (same precision)
+ *   for such shapes.
  *
  * Status codes: every call returns a cpg_status (0 = success, < 0 = error).
  * On error no caller buffer is freed; outputs are unspecified unless stated.
@@ -84,7 +90,9 @@ typedef enum {
                                   2's n* (any split gives the same gradients, eqs. 3.7 =
                                   3.8); 0 restores the default                         */
     CPG_OPT_KERNEL = 2,        /* 0 = automatic, 1 = force the generic vector-ALU
-                                  contraction, 2 = force the MFMA contraction           */
+                                  contraction (native mode only), 2 = force the MFMA
+                                  contraction; CPG_ERR_UNSUPPORTED (settings kept)
+                                  when the plan cannot honour it                      */
     CPG_OPT_PROFILE = 3,       /* 1: bracket every big-contraction launch with a pair of
                                   HIP events on the plan's stream (read them with
                                   cpgrad_profile_read); 0: off (default)               */
@@ -107,6 +115,13 @@ int cpgrad_plan(cpgrad_plan_t* out, int N, const int64_t* dims, int R,
  * factors + gradients).  Any output pointer may be NULL. */
 int cpgrad_plan_info(cpgrad_plan_t p, int* n_star, size_t* workspace_bytes,
                      double* alg_flops_all_modes, double* alg_bytes_all_modes);
+
+/* Which kernels the plan runs (host query, no device work): the contraction
+ * kernel of its passes (1 = generic vector-ALU kernel, 2 = float32 matrix
+ * cores, 3 = bf16 matrix cores) and whether the split partials are reduced by
+ * the fused multi-block reduction (1) or the generic one (0).  Either output
+ * pointer may be NULL.  Errors: CPG_ERR_INVALID. */
+int cpgrad_plan_path(cpgrad_plan_t p, int* contraction_kernel, int* fused_reduction);
 
 /* Host-only planning query (touches no device): the n* that a plan for this
  * shape would use (Algorithm 2, step 1; force_nstar in [1, N-1] overrides it,

@@ -33,7 +33,7 @@ EXPORTS = ["cpgrad_plan", "cpgrad_plan_info", "cpgrad_query", "cpgrad_set_option
            "cpgrad_status_string", "cpgrad_version",
            "cpmlp_create", "cpmlp_num_params", "cpmlp_set_params", "cpmlp_get_params", "cpmlp_forward",
            "cpmlp_gradients", "cpmlp_train_step", "cpmlp_destroy", "cpals_features", "cp_fit_extrapolated",
-           "cpals_learned_step", "cpgrad_all_modes_noalloc"]
+           "cpals_learned_step", "cpgrad_all_modes_noalloc", "cpgrad_plan_path"]
 NFEAT = 12
 
 
@@ -54,6 +54,7 @@ def _load():
                                        ctypes.c_int, ctypes.c_int, vp]),
         "cpgrad_plan_info": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_size_t),
                                             dp, dp]),
+        "cpgrad_plan_path": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
         "cpgrad_query": (ctypes.c_int, [ctypes.c_int, i64p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_int), dp, dp]),
         "cpgrad_set_option": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int64]),
@@ -176,6 +177,13 @@ def cpgrad_plan_info(plan):
     _check(LIB.cpgrad_plan_info(plan.handle, ctypes.byref(ns), ctypes.byref(ws), ctypes.byref(fl),
                                 ctypes.byref(by)), "cpgrad_plan_info")
     return {"n_star": ns.value, "workspace_bytes": ws.value, "alg_flops": fl.value, "alg_bytes": by.value}
+
+
+def cpgrad_plan_path(plan):
+    """dict(kernel: 1 generic / 2 float32 MFMA / 3 bf16 MFMA, fused_reduction: bool)."""
+    k, f = ctypes.c_int(), ctypes.c_int()
+    _check(LIB.cpgrad_plan_path(plan.handle, ctypes.byref(k), ctypes.byref(f)), "cpgrad_plan_path")
+    return {"kernel": k.value, "fused_reduction": bool(f.value)}
 
 
 def cpgrad_query(dims, R, y_dtype="f32", factor_dtype=None, force_nstar=0):

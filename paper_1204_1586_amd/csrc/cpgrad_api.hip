@@ -124,13 +124,50 @@ static Tiling tile_mfma(int64_t J, int64_t K, int R, int roles, int kernel, int6
     return t;
 }
 
-// 0 = generic kernel, 2 = float32 MFMA, 3 = bf16 MFMA (reduced-precision modes)
+// Can the matrix-core kernels take a J x K view at all?  32-bit buffer
+// offsets (a 32-column step of Y below 2 GiB), row and column indices that
+// the kernels unravel by 32-bit multiply-shift division (below 2^31), and a
+// grid whose column dimension stays within 65535 blocks.
+static bool mfma_shape_ok(const cpgrad_plan_s* p, int kind) {
+    const int64_t lim = int64_t(1) << 31;
+    if (p->J * 4 * 32 >= lim || p->J >= lim || p->K >= lim) return false;
+    const bool klo = p->mode == CPG_MODE_BF16_REFINED;
+    for (int roles = 1; roles <= 3; ++roles) {
+        const Tiling t = tile_mfma(p->J, p->K, p->R, roles, kind, p->opt_cols, klo && p->ydt == CPG_F32, klo,
+                                   fac_stage_floats(p->N, p->dims, p->R));
+        if (t.n_kc > 65535 || t.n_jr > 0x7fffffff) return false;
+    }
+    return true;
+}
+
+// The matrix-core kind a plan's types and mode ask for: 2 = float32 MFMA
+// (native float32), 3 = bf16 MFMA (the bf16 modes), 0 = none (float64).
+static int wanted_kind(const cpgrad_plan_s* p) {
+    if (p->mode != CPG_MODE_NATIVE) return 3;
+    return (p->ydt == CPG_F32 && p->fdt == CPG_F32) ? 2 : 0;
+}
+
+// 0 = generic kernel, 2 = float32 MFMA, 3 = bf16 MFMA (reduced-precision modes).
+// The native float32 form falls back to the generic kernel (same precision)
+// when the matrix cores cannot take the shape; a reduced-precision mode never
+// does (plan_kind_ok refuses the plan instead).
 static int mfma_kind(const cpgrad_plan_s* p) {
-    // 32-bit buffer offsets: a 32-column step of Y stays below 2 GiB
-    if (p->kernel_opt == 1 || p->J * 4 * 32 >= (int64_t(1) << 31)) return 0;
-    if (p->mode == CPG_MODE_NATIVE)
-        return (p->ydt == CPG_F32 && p->fdt == CPG_F32 && (p->J % 4) == 0) ? 2 : 0;
-    return (p->fdt == CPG_F32 && (p->ydt == CPG_F32 || p->ydt == CPG_BF16) && (p->J % 8) == 0) ? 3 : 0;
+    const int kind = wanted_kind(p);
+    if (kind == 0 || p->kernel_opt == 1) return 0;
+    const int64_t align = kind == 2 ? 4 : 8;   // rows per MFMA operand chunk
+    if (p->J % align != 0 || !mfma_shape_ok(p, kind)) return 0;
+    return kind;
+}
+
+// A plan whose mode or forced kernel cannot be honoured is refused: the bf16
+// modes need the bf16 matrix cores (J a multiple of 8 and a shape they can
+// take), CPG_OPT_KERNEL = 2 needs a matrix-core kind, and the reduced-precision
+// modes cannot be forced onto the generic (full-precision) kernel.
+static int plan_kind_ok(const cpgrad_plan_s* p) {
+    const int kind = mfma_kind(p);
+    if (p->mode != CPG_MODE_NATIVE && kind != 3) return CPG_ERR_UNSUPPORTED;
+    if (p->kernel_opt == 2 && kind == 0) return CPG_ERR_UNSUPPORTED;
+    return CPG_OK;
 }
 
 static Tiling tile_pass(const cpgrad_plan_s* p, int roles) {
@@ -159,6 +196,10 @@ static int configure(cpgrad_plan_s* p) {
     p->nstar = p->force_nstar ? p->force_nstar : p->nstar_auto;
     p->J = p->Jn[p->nstar];
     p->K = p->Kn[p->nstar];
+    {
+        const int st = plan_kind_ok(p);
+        if (st) return st;
+    }
     p->t_fused = tile_pass(p, 3);
     p->t_right = tile_pass(p, 1);
     p->t_left = tile_pass(p, 2);
@@ -812,7 +853,10 @@ static int plan_init(cpgrad_plan_s* p, int N, const int64_t* dims, int R, int y_
     for (int n = N - 1; n >= 0; --n) p->Kn[n] = p->Kn[n + 1] * dims[n];
     // Algorithm 2, step 1: n* = max{n : J_n <= K_n}, n in [1, N-1]; 1 if none
     p->nstar_auto = default_nstar(N, dims);
-    return CPG_OK;
+    p->nstar = p->nstar_auto;
+    p->J = p->Jn[p->nstar];
+    p->K = p->Kn[p->nstar];
+    return plan_kind_ok(p);
 }
 
 // Enqueue the all-mode gradient on a configured plan.
@@ -928,6 +972,13 @@ int cpgrad_plan_info(cpgrad_plan_t p, int* n_star, size_t* workspace_bytes, doub
     return CPG_OK;
 }
 
+int cpgrad_plan_path(cpgrad_plan_t p, int* contraction_kernel, int* fused_reduction) {
+    if (!p) return CPG_ERR_INVALID;
+    if (contraction_kernel) *contraction_kernel = p->t_fused.kernel;
+    if (fused_reduction) *fused_reduction = p->fused_first ? 1 : 0;
+    return CPG_OK;
+}
+
 int cpgrad_profile_read(cpgrad_plan_t p, int roles, double* total_ms, int64_t* launches) {
     if (!p || roles < 0 || roles > 3) return CPG_ERR_INVALID;
     if (hipStreamSynchronize(p->stream) != hipSuccess) return CPG_ERR_HIP;
@@ -953,6 +1004,8 @@ int cpgrad_set_option(cpgrad_plan_t p, int option, int64_t value) {
         p->ev_used = 0;
         return CPG_OK;
     }
+    const int old_nstar = p->force_nstar, old_kernel = p->kernel_opt;
+    const int64_t old_cols = p->opt_cols;
     if (option == CPG_OPT_FORCE_NSTAR) {
         if (value != 0 && (value < 1 || value > p->N - 1)) return CPG_ERR_INVALID;
         p->force_nstar = (int)value;
@@ -966,8 +1019,19 @@ int cpgrad_set_option(cpgrad_plan_t p, int option, int64_t value) {
         return CPG_ERR_INVALID;
     }
     const void* b = p->bound;
-    const int st = configure(p);
-    if (st == CPG_OK && b) return cpgrad_bind(p, b);
+    int st = configure(p);
+    if (st == CPG_ERR_UNSUPPORTED) {
+        // the option cannot be honoured for this plan: keep the previous settings
+        p->force_nstar = old_nstar;
+        p->kernel_opt = old_kernel;
+        p->opt_cols = old_cols;
+        const int st2 = configure(p);
+        if (st2) return st2;
+    }
+    if (b) {
+        const int sb = cpgrad_bind(p, b);
+        if (sb) return sb;
+    }
     return st;
 }
 

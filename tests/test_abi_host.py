@@ -120,3 +120,15 @@ def test_noalloc_rejects_bad_arguments_before_any_device_call():
     nulls = (vp * 3)(16, None, 48)
     assert f(3, dims, 3, 1, 1, 0, vp(16), nulls, ptrs, None) == -1             # a NULL factor
     assert P.LIB.cpgrad_status_string(-7).decode().startswith("CPG_ERR_SCRATCH")
+
+
+def test_reduced_precision_mode_is_refused_where_matrix_cores_cannot_run():
+    """A bf16 mode never falls back silently to the full-precision kernel: a
+    split whose row count J = I_1...I_n* is not a multiple of 8 is refused
+    before any device call."""
+    assert _plan_status(3, [5, 6, 7], 3, ydt=1, fdt=1, mode=1) == -5        # n* = 1, J = 5
+    assert _plan_status(3, [5, 6, 7], 3, ydt=2, fdt=1, mode=2) == -5
+    dims = (ctypes.c_int64 * 3)(5, 6, 7)
+    vp = ctypes.c_void_p
+    ptrs = (vp * 3)(16, 32, 48)
+    assert P.LIB.cpgrad_all_modes_noalloc(3, dims, 3, 1, 1, 2, vp(16), ptrs, ptrs, None) == -5

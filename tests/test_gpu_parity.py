@@ -1,14 +1,16 @@
 """GPU parity: the HIP path (through the C ABI) against the float64 oracle on
-identical seeded inputs.  Tolerances (relative Frobenius error per mode):
-1e-12 for float64, 1e-5 for float32; bf16-stored tensors are compared with
-the oracle run on the exact stored values."""
+identical seeded inputs.  Gradients are compared entry by entry
+(gpu_util.check_gradients): relative Frobenius error and max|dG|/max|G_ref|
+per mode within 1e-12 (float64) / 1e-5 (float32), and every entry within its
+rounding bound against the magnitude gradient; bf16-stored tensors are
+compared with the oracle run on the exact stored values."""
 import numpy as np
 import pytest
 import torch
 
 import oracle as O
-from gpu_util import (exact_factors, exact_tensor, factor_storage, problem, rel_fro, to_device_factors,
-                      to_device_y)
+from gpu_util import (check_gradients, exact_factors, exact_tensor, factor_storage, magnitude_gradients, problem,
+                      rel_fro, to_device_factors, to_device_y)
 
 pytestmark = pytest.mark.gpu
 
@@ -45,7 +47,22 @@ CASES = [
     ((36, 20, 28, 33), 48, "f32"),
     ((8, 600, 7), 64, "f32"),
     ((12, 40, 36, 10), 20, "f32"),
+    ((6, 5, 4, 6, 5, 4, 6), 10, "f32"),       # 7-D, J_{n*} = 120: float32 matrix cores, three-mode chains
+    ((4, 3, 5, 4, 3, 2, 6), 10, "f32"),       # 7-D, J_{n*} = 60
+    ((10, 1, 12, 1, 8), 6, "f32"),            # unit modes
+    ((4, 65, 300), 5, "f32"),                 # J = 260: a 256-row block plus a ragged 4-row one
 ]
+
+
+def _form(storage, mode="native"):
+    return storage if mode == "native" else mode
+
+
+def _check(pr, A, G, storage, mode="native", label=""):
+    Y = exact_tensor(pr["y"], storage, pr["dims"])
+    Ax = exact_factors(A)
+    ref = O.cp_gradient_all(Y, Ax)
+    return check_gradients(G, ref, magnitude_gradients(Y, Ax), _form(storage, mode), label)
 
 
 @pytest.mark.parametrize("dims,R", [((20, 30, 40, 50), 16), ((36, 20, 28, 33), 48), ((100, 77), 5),
@@ -54,11 +71,10 @@ CASES = [
 def test_both_contraction_kernels_match_oracle(dims, R, kernel):
     """The vector-ALU and the MFMA contraction reach the oracle's gradients."""
     print(f"[kernel {kernel}] dims={dims} R={R}", flush=True)
-    pr, A, G, _ = _all_modes(dims, R, "f32", kernel=kernel)
-    Y = exact_tensor(pr["y"], "f32", dims)
-    ref = O.cp_gradient_all(Y, exact_factors(A))
-    for n in range(len(dims)):
-        assert rel_fro(G[n], ref[n]) <= 1e-5, (n, rel_fro(G[n], ref[n]))
+    import paper_1204_1586_amd as P
+    pr, A, G, plan = _all_modes(dims, R, "f32", kernel=kernel)
+    assert P.cpgrad_plan_path(plan)["kernel"] == (1 if kernel == 1 else 2)
+    _check(pr, A, G, "f32", label=f"kernel {kernel}")
 
 
 @pytest.mark.parametrize("dims,R,storage", CASES)
@@ -66,20 +82,43 @@ def test_all_modes_matches_oracle(dims, R, storage):
     print(f"[all_modes] dims={dims} R={R} storage={storage}", flush=True)
     mode = "native" if storage != "bf16" else "bf16_refined"
     pr, A, G, _ = _all_modes(dims, R, storage, mode)
-    Y = exact_tensor(pr["y"], storage, dims)
-    ref = O.cp_gradient_all(Y, exact_factors(A))
-    for n in range(len(dims)):
-        assert rel_fro(G[n], ref[n]) <= TOL[storage], (n, rel_fro(G[n], ref[n]))
+    _check(pr, A, G, storage, mode, label=str(dims))
+
+
+def test_7d_float32_takes_the_matrix_cores():
+    """The float32 7-D case with J_{n*} = 120 runs the float32 MFMA contraction
+    and the fused reduction (three-mode right and left chains)."""
+    import paper_1204_1586_amd as P
+    pr, A, G, plan = _all_modes((6, 5, 4, 6, 5, 4, 6), 10, "f32")
+    path = P.cpgrad_plan_path(plan)
+    assert path["kernel"] == 2 and path["fused_reduction"], path
 
 
 def test_full_size_64_4_f32():
     dims, R = (64, 64, 64, 64), 16
     print(f"[all_modes full] dims={dims} R={R}", flush=True)
     pr, A, G, plan = _all_modes(dims, R, "f32")
-    Y = exact_tensor(pr["y"], "f32", dims)
-    ref = O.cp_gradient_all(Y, exact_factors(A))
-    for n in range(4):
-        assert rel_fro(G[n], ref[n]) <= 1e-5, (n, rel_fro(G[n], ref[n]))
+    _check(pr, A, G, "f32", label="64^4")
+
+
+def test_full_size_7d_f32():
+    """The 10^7, rank-10, 20 dB float32 workload at full size in the launch
+    configuration the library picks (float32 matrix cores, J = 1000,
+    three-mode chains on both sides): every entry of every mode's 10 x 10
+    gradient against the oracle."""
+    import cpgen
+    import paper_1204_1586_amd as P
+    w = cpgen.WORKLOADS["cp7d_10_r10_f32"]
+    print(f"[all_modes full] dims={w.dims} R={w.rank} f32", flush=True)
+    pr = cpgen.make_problem(w, rep=0)
+    Y = to_device_y(pr["y"], "f32")
+    A = to_device_factors(pr["init"], "f32")
+    G = [torch.empty_like(M) for M in A]
+    plan = P.cpgrad_plan(pr["dims"], pr["R"], "f32", "f32")
+    assert P.cpgrad_plan_path(plan)["kernel"] == 2
+    P.cpgrad_all_modes(plan, Y, A, G)
+    torch.cuda.synchronize()
+    _check(pr, A, [g.cpu().double().numpy() for g in G], "f32", label="10^7")
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])
@@ -91,11 +130,8 @@ def test_any_split_gives_the_same_gradients(storage):
     for ns in range(1, 5):
         pr, A, G, _ = _all_modes(dims, R, storage, force_nstar=ns)
         outs.append(G)
-    Y = exact_tensor(pr["y"], storage, dims)
-    ref = O.cp_gradient_all(Y, exact_factors(A))
-    for G in outs:
-        for n in range(5):
-            assert rel_fro(G[n], ref[n]) <= TOL[storage]
+    for ns, G in enumerate(outs, start=1):
+        _check(pr, A, G, storage, label=f"n*={ns}")
 
 
 def test_deterministic():
@@ -121,14 +157,77 @@ def _als_setup(dims, R, storage, mode="native", seed=0, snr=25.0):
     return P, pr, Y, A, plan
 
 
-@pytest.mark.parametrize("dims,R,storage,ftol", [((20, 20, 20), 3, "f64", 1e-10), ((11, 13, 9, 7), 5, "f64", 1e-10),
-                                                 ((20, 30, 40, 50), 16, "f32", 2e-4),
-                                                 ((36, 20, 28, 33), 24, "f32", 2e-4),
-                                                 ((5, 6, 3, 4, 2, 3, 5), 10, "f32", 2e-4),
-                                                 ((64, 64, 64, 64), 16, "f32", 2e-4),
-                                                 ((8, 9, 10), 3, "f32", 2e-4),
-                                                 ((12, 10, 14, 9), 7, "f32", 2e-4)])
-def test_als_sweep_matches_oracle(dims, R, storage, ftol):
+EPS_G = {"f64": 1e-12, "f32": 1e-5, "bf16_refined": 2.1e-5}
+
+
+def _sweep_states(Yx, A_start, A_end):
+    """For each mode m in the Section 4 order, the factor set its update of
+    eq. 2.14 saw: modes updated before m at their end-of-sweep values, the
+    rest at their start values."""
+    N = Yx.ndim
+    order = O.als_order(N, O.n_star(Yx.shape))
+    pos = {m: i for i, m in enumerate(order)}
+    for m in order:
+        yield m, [A_end[k] if pos[k] < pos[m] else A_start[k] for k in range(N)]
+
+
+def _backward_errors(Yx, A_start, A_end):
+    """Normwise backward error of every update of one sweep:
+    eta_m = ||A_m Gamma_m - G_m|| / (||A_m|| ||Gamma_m|| + ||G_m||), with G_m and
+    Gamma_m (eq. 2.14) formed by the oracle from the factors that update saw.
+    It does not grow with the conditioning of Gamma: a solve of the exact
+    normal equations from a gradient with relative error eps, stored in
+    float32, has eta <= eps + u."""
+    out, kap = {}, {}
+    for m, S in _sweep_states(Yx, A_start, A_end):
+        Gam = O.gamma(S, m)
+        G = O.mttkrp(Yx, S, m)
+        r = A_end[m] @ Gam - G
+        out[m] = float(np.linalg.norm(r) / (np.linalg.norm(A_end[m]) * np.linalg.norm(Gam) + np.linalg.norm(G)))
+        kap[m] = float(np.linalg.cond(Gam))
+    return out, kap
+
+
+def _als_bounds(Yx, A_start, A_end, form, sweeps=1):
+    """Bounds derived from the arithmetic, for a sweep (or `sweeps` sweeps)
+    from A_start that ended at A_end (both sides' factors), eps = the gradient
+    tolerance of the form:
+    eta   : backward error of each update <= eps (see _backward_errors);
+    tol_a : forward error of the factors against the oracle's: a solve with a
+            right-hand side of relative error eps is accurate to kappa eps, and
+            each update inherits the errors of the earlier ones, so
+            tol_a = sweeps N max(kappa) eps;
+    tol_d : cost of eq. 2.12 by the expanded identity: ||Y||^2 and ||Yhat||^2
+            (float64 Grams of the stored factors) are exact to float64
+            rounding, <Y, Yhat> = sum G^(N) .* A^(N) carries the gradient's
+            error: |dD| <= 2 eps ||G^(N)|| ||A^(N)||;
+    tol_f : fit = 1 - sqrt(D)/||Y|| of the device against the explicit residual
+            of its own factors: |dfit| <= tol_d / (2 sqrt(D) ||Y||);
+    tol_s : fit of the device's factors against the oracle's, first order in
+            the factor differences: dD = sum_m <dD/dA_m, dA_m> with
+            dD/dA_m = -2 (G_m - A_m Gamma_m) (eq. 2.13), |dA_m| <= tol_a |A_m|."""
+    eps = EPS_G[form]
+    N = Yx.ndim
+    _, kap = _backward_errors(Yx, A_start, A_end)
+    kmax = max(kap.values())
+    tol_a = sweeps * N * kmax * eps
+    GN = O.mttkrp(Yx, A_end, N - 1)
+    y2 = O.norm2(Yx)
+    tol_d = 2 * eps * np.linalg.norm(GN) * np.linalg.norm(A_end[N - 1]) + 1e-13 * y2
+    D = O.cost_explicit(Yx, A_end)
+    den = 2 * np.sqrt(max(D, 1e-300)) * np.sqrt(y2)
+    E = O.e_gradient_all(Yx, A_end)
+    dD = sum(2 * np.linalg.norm(E[m]) * tol_a * np.linalg.norm(A_end[m]) for m in range(N))
+    return {"kappa": kmax, "tol_a": tol_a, "tol_d": tol_d, "tol_f": tol_d / den, "tol_s": (tol_d + dD) / den,
+            "D": D}
+
+
+@pytest.mark.parametrize("dims,R,storage", [((20, 20, 20), 3, "f64"), ((11, 13, 9, 7), 5, "f64"),
+                                            ((20, 30, 40, 50), 16, "f32"), ((36, 20, 28, 33), 24, "f32"),
+                                            ((5, 6, 3, 4, 2, 3, 5), 10, "f32"), ((6, 5, 4, 6, 5, 4, 6), 10, "f32"),
+                                            ((64, 64, 64, 64), 16, "f32"), ((8, 9, 10), 3, "f32"),
+                                            ((12, 10, 14, 9), 7, "f32")])
+def test_als_sweep_matches_oracle(dims, R, storage):
     print(f"[als] dims={dims} R={R} storage={storage}", flush=True)
     P, pr, Y, A, plan = _als_setup(dims, R, storage)
     A0 = exact_factors(A)
@@ -136,13 +235,27 @@ def test_als_sweep_matches_oracle(dims, R, storage, ftol):
     Yx = exact_tensor(pr["y"], storage, dims)
     A_ref, D_ref, fit_ref = O.als_sweep(Yx, A0)
     A_gpu = exact_factors(A)
-    for n in range(len(dims)):
-        assert rel_fro(A_gpu[n], A_ref[n]) <= ftol, (n, rel_fro(A_gpu[n], A_ref[n]))
-    ctol = 1e-10 if storage == "f64" else 1e-4
-    assert abs(cost - D_ref) <= ctol * O.norm2(Yx)
-    assert abs(fit - fit_ref) <= (1e-10 if storage == "f64" else 1e-4)
-    # the device's cost is the explicit residual of the model it returned
-    assert abs(cost - O.cost_explicit(Yx, A_gpu)) <= ctol * O.norm2(Yx)
+    _check_sweep(Yx, A0, A_gpu, A_ref, cost, fit, fit_ref, storage)
+
+
+def _check_sweep(Yx, A_start, A_gpu, A_ref, cost, fit, fit_ref, form, sweeps=1, A_last_start=None):
+    """Checks of one or more sweeps of the device against the oracle's from the
+    same start (A_last_start: the device's factors at the start of its last
+    sweep, for the backward errors)."""
+    N = Yx.ndim
+    eta, _ = _backward_errors(Yx, A_last_start if A_last_start is not None else A_start, A_gpu)
+    b = _als_bounds(Yx, A_start, A_gpu, form, sweeps)
+    ferr = max(rel_fro(A_gpu[n], A_ref[n]) for n in range(N))
+    fit_x = O.fit_from_cost(b["D"], O.norm2(Yx))
+    print(f"  backward err {max(eta.values()):.1e} (tol {EPS_G[form]:.0e}); kappa {b['kappa']:.1f}: factor err "
+          f"{ferr:.2e} (tol {b['tol_a']:.1e}); cost vs explicit {abs(cost - b['D']) / O.norm2(Yx):.1e}·||Y||^2 "
+          f"(tol {b['tol_d'] / O.norm2(Yx):.1e}); fit vs explicit {abs(fit - fit_x):.1e} (tol {b['tol_f']:.1e}); "
+          f"fit vs oracle {abs(fit - fit_ref):.1e} (tol {b['tol_f'] + b['tol_s']:.1e})", flush=True)
+    assert max(eta.values()) <= EPS_G[form], eta
+    assert ferr <= b["tol_a"]
+    assert abs(cost - b["D"]) <= b["tol_d"]
+    assert abs(fit - fit_x) <= b["tol_f"]
+    assert abs(fit - fit_ref) <= b["tol_f"] + b["tol_s"]
 
 
 def test_als_50_sweeps_3d_f64():
@@ -155,25 +268,119 @@ def test_als_50_sweeps_3d_f64():
     plan = P.cpgrad_plan(pr["dims"], pr["R"], "f64", "f64")
     P.cpgrad_bind(plan, Y)
     fits = [P.cpals_step(plan, Y, A)[1] for _ in range(50)]
-    _, fits_ref = O.cp_als(exact_tensor(pr["y"], "f64", pr["dims"]), pr["init"], 50)
-    assert np.max(np.abs(np.array(fits) - np.array(fits_ref))) <= 1e-10
+    A_ref, fits_ref = O.cp_als(exact_tensor(pr["y"], "f64", pr["dims"]), pr["init"], 50)
+    d = np.max(np.abs(np.array(fits) - np.array(fits_ref)))
+    print(f"  max |fit - fit_oracle| over 50 sweeps: {d:.2e}", flush=True)
+    assert d <= 1e-10
     assert fits[-1] > 0.9
+    for n in range(3):
+        assert rel_fro(exact_factors(A)[n], A_ref[n]) <= 1e-9
+
+
+def _sweeps(P, plan, Y, A, k):
+    """k device sweeps; returns (fits, factors at the start of the last sweep)."""
+    fits = []
+    for s in range(k):
+        if s == k - 1:
+            A_last = exact_factors(A)
+        fits.append(P.cpals_step(plan, Y, A)[1])
+    return fits, A_last
 
 
 def test_als_sweeps_f32_track_oracle():
     """Five float32 sweeps on 20x30x40x50, rank 16 (both passes on the many-block
     epilogue, Grams carried from sweep to sweep): fits and factors stay with the
-    oracle's float64 sweeps from the same start."""
+    oracle's float64 sweeps from the same start, within the derived bounds."""
     dims, R = (20, 30, 40, 50), 16
     print(f"[als x5] dims={dims} R={R}", flush=True)
     P, pr, Y, A, plan = _als_setup(dims, R, "f32")
     A0 = exact_factors(A)
-    fits = [P.cpals_step(plan, Y, A)[1] for _ in range(5)]
-    A_ref, fits_ref = O.cp_als(exact_tensor(pr["y"], "f32", dims), A0, 5)
-    assert np.max(np.abs(np.array(fits) - np.array(fits_ref))) <= 1e-4, (fits, fits_ref)
-    A_gpu = exact_factors(A)
-    for n in range(len(dims)):
-        assert rel_fro(A_gpu[n], A_ref[n]) <= 1e-3, (n, rel_fro(A_gpu[n], A_ref[n]))
+    fits, A_last = _sweeps(P, plan, Y, A, 5)
+    Yx = exact_tensor(pr["y"], "f32", dims)
+    A_ref, fits_ref = O.cp_als(Yx, A0, 5)
+    print(f"  max fit diff over the sweeps {np.max(np.abs(np.array(fits) - np.array(fits_ref))):.1e}", flush=True)
+    _check_sweep(Yx, A0, exact_factors(A), A_ref, P.cpgrad_last_fit(plan)[0], fits[-1], fits_ref[-1], "f32",
+                 sweeps=5, A_last_start=A_last)
+
+
+def test_als_100_sweeps_64_4_f32_track_oracle():
+    """The 64^4, rank-16, 20 dB float32 workload: 100 sweeps from the seeded
+    start against the float64 oracle's 100 sweeps (stored by
+    tests/golden/make_als100_cp4d_64_r16.py from the oracle alone).  Both runs
+    reach the same point: the last fits agree to the 1e-6 scale of the
+    |delta fit| stopping rule, and so do the factors.  On the way the two
+    trajectories separate by up to ~1e-5 in fit in the sweeps where ALS still
+    moves fast (float32 rounding of the gradients, amplified by the iteration);
+    the per-sweep difference is reported and held below 1e-4."""
+    import json
+    import os
+    import cpgen
+    import paper_1204_1586_amd as P
+    with open(os.path.join(os.path.dirname(__file__), "golden", "als100_cp4d_64_r16.json")) as f:
+        gold = json.load(f)
+    pr = cpgen.make_problem("cp4d_64_r16_f32", rep=0)
+    Y = to_device_y(pr["y"], "f32")
+    A = to_device_factors(pr["init"], "f32")
+    plan = P.cpgrad_plan(pr["dims"], pr["R"], "f32", "f32")
+    P.cpgrad_bind(plan, Y)
+    fits = np.array([P.cpals_step(plan, Y, A)[1] for _ in range(gold["sweeps"])])
+    d = np.abs(fits - np.array(gold["fits"]))
+    print(f"  |fit - fit_oracle|: sweep 1 {d[0]:.2e}, max {d.max():.2e} (sweep {int(d.argmax()) + 1}), "
+          f"sweeps 50-100 max {d[49:].max():.2e}, last {d[-1]:.2e}", flush=True)
+    print("  per sweep: " + " ".join(f"{x:.1e}" for x in d), flush=True)
+    assert d.max() <= 1e-4
+    assert d[-1] <= 1e-6
+    norms = [float(torch.linalg.norm(M.double())) for M in A]
+    assert np.allclose(norms, gold["final_factor_norms"], rtol=1e-4), (norms, gold["final_factor_norms"])
+
+
+def _congruent_setup(workload, rep, dims, R, storage, mode):
+    import cpgen
+    import paper_1204_1586_amd as P
+    pr = cpgen.make_problem(workload, rep=rep, dims=dims, rank=R, storage=storage)
+    Y = to_device_y(pr["y"], storage)
+    plan = P.cpgrad_plan(pr["dims"], pr["R"], storage, "f32", mode)
+    P.cpgrad_bind(plan, Y)
+    return P, pr, Y, plan
+
+
+@pytest.mark.parametrize("start", ["seeded", "near_truth"])
+def test_als_congruent_0_9_matches_oracle(start):
+    """Collinear factors (pairwise column congruence 0.9, 30 dB) at the
+    40x50x60x70 shape of the learned-step tensors, float32: Gamma is at its worst
+    conditioned near the true factors, so besides the seeded start one sweep
+    starts from the truth perturbed by 5 % noise."""
+    P, pr, Y, plan = _congruent_setup("cp4d_40x70_learned", 10500, None, None, "f32", "native")
+    dims, R = pr["dims"], pr["R"]
+    print(f"[als congruent 0.9] dims={dims} R={R} start={start}", flush=True)
+    if start == "seeded":
+        A = to_device_factors(pr["init"], "f32")
+    else:
+        g = np.random.default_rng(11)
+        A = to_device_factors([M + 0.05 * np.std(M) * g.standard_normal(M.shape) for M in pr["truth"]], "f32")
+    A0 = exact_factors(A)
+    k = 3 if start == "seeded" else 1
+    fits, A_last = _sweeps(P, plan, Y, A, k)
+    Yx = exact_tensor(pr["y"], "f32", dims)
+    A_ref, fits_ref = O.cp_als(Yx, A0, k)
+    _check_sweep(Yx, A0, exact_factors(A), A_ref, P.cpgrad_last_fit(plan)[0], fits[-1], fits_ref[-1], "f32",
+                 sweeps=k, A_last_start=A_last)
+
+
+def test_als_congruent_0_5_bf16_refined_matches_oracle():
+    """Congruence-0.5 factors, 25 dB, tensor stored in bf16 (a small version of
+    the 48^5 workload), ALS on the refined bf16 contraction: two sweeps against
+    the oracle's on the exact stored values, within the refined form's bounds."""
+    P, pr, Y, plan = _congruent_setup("cp5d_48_r32_bf16", 10600, (16, 12, 10, 8, 8), 8, "bf16", "bf16_refined")
+    dims = pr["dims"]
+    print(f"[als congruent 0.5 bf16] dims={dims} R={pr['R']}", flush=True)
+    A = to_device_factors(pr["init"], "f32")
+    A0 = exact_factors(A)
+    fits, A_last = _sweeps(P, plan, Y, A, 2)
+    Yx = exact_tensor(pr["y"], "bf16", dims)
+    A_ref, fits_ref = O.cp_als(Yx, A0, 2)
+    _check_sweep(Yx, A0, exact_factors(A), A_ref, P.cpgrad_last_fit(plan)[0], fits[-1], fits_ref[-1],
+                 "bf16_refined", sweeps=2, A_last_start=A_last)
 
 
 @pytest.mark.parametrize("dims,R,storage", [((20, 20, 20), 3, "f64"), ((20, 30, 40, 50), 16, "f32"),
