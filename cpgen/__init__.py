@@ -217,3 +217,23 @@ def random_tensor(dims, g: np.random.Generator, storage="f64"):
     if storage == "bf16":
         return to_bf16_bits(x)
     return x.astype({"f64": np.float64, "f32": np.float32}[storage])
+
+
+NTF_WORKLOAD_ID = 6
+
+
+def make_nonnegative_problem(dims, R, rep=0, snr_db=30.0, storage="f32"):
+    """A seeded nonnegative CP problem (for the multiplicative update of
+    eq. 2.18): true factors i.i.d. U(0, 1), Y = max([[A]] + E, 0) with E at the
+    given SNR (entries clipped at zero after the noise, before the cast), and
+    initial factors i.i.d. U(0.1, 1.1).  storage: 'f64' or 'f32'."""
+    dims = tuple(int(d) for d in dims)
+    R = int(R)
+    g_true = rng(NTF_WORKLOAD_ID, rep, STREAM_TRUE)
+    truth = [g_true.uniform(0.0, 1.0, (I, R)) for I in dims]
+    y = noisy_cp_tensor(truth, snr_db, rng(NTF_WORKLOAD_ID, rep, STREAM_NOISE), storage)
+    np.maximum(y, 0, out=y)
+    g = rng(NTF_WORKLOAD_ID, rep, STREAM_INIT)
+    init = [g.uniform(0.1, 1.1, (I, R)) for I in dims]
+    return {"dims": dims, "R": R, "storage": storage, "y": y, "truth": truth, "init": init,
+            "workload": "ntf_nonnegative", "rep": rep, "snr_db": snr_db}

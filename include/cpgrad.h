@@ -175,6 +175,45 @@ int cp_fit(cpgrad_plan_t p, const void* Y, const void* const* A,
  * cpals_step / cp_fit, with its status (CPG_ERR_NOT_SPD / CPG_ERR_NONFINITE). */
 int cpgrad_last_fit(cpgrad_plan_t p, double* cost_out, double* fit_out);
 
+/* The full gradient of eq. 2.13 for all modes at once, without its factor -2
+ * (the gradient all-at-once methods step along, eqs. 2.15 - 2.17):
+ *   E[n] <- Y_(n) (⊙_{k≠n} A^(k)) - A^(n) Gamma^(n),
+ *   Gamma^(n) = ⊛_{k≠n} A^(k)T A^(k)  (float64 Grams),
+ * i.e. the CP gradients of cpgrad_all_modes (one fused pass over Y, Algorithm
+ * 2) minus A^(n) Gamma^(n), formed in float64 and rounded once to the factor
+ * type.  E (host array of N device pointers, I_n x R row-major) must not alias
+ * A or Y.  Vanishes at an exact model Y = [[A]].  Asynchronous.
+ * Errors: CPG_ERR_INVALID, CPG_ERR_HIP. */
+int cpgrad_e_gradient(cpgrad_plan_t p, const void* Y, const void* const* A, void* const* E);
+
+/* The CP gradient of one mode n (1-based) by Section 3.2: one pass over Y.
+ * If J_n <= K_{n-1} (and n < N, or n = 1) the right-to-left way: P_R =
+ * Y_(1:n) (A^(N) (.) ... (.) A^(n+1)) (eq. 3.10), then the leading J_{n-1}
+ * rows contracted with A^(n-1) (.) ... (.) A^(1) (eq. 3.12); otherwise the
+ * left-to-right way: P_L = (A^(n-1) (.) ... (.) A^(1))^T Y_(1:n-1) (eq. 3.9),
+ * then the trailing K_n columns contracted with A^(N) (.) ... (.) A^(n+1)
+ * (eq. 3.16).  G: I_n x R device buffer (row-major, factor type).
+ * direction (may be NULL) receives 0 for right-to-left, 1 for left-to-right.
+ * The plan allocates the buffers of that pass on first use (grown as needed).
+ * A reduced-precision plan takes the other way if its matrix cores cannot
+ * take the first split.  Asynchronous.
+ * Errors: CPG_ERR_INVALID (n outside [1, N], NULL), CPG_ERR_UNSUPPORTED,
+ * CPG_ERR_NOMEM, CPG_ERR_HIP. */
+int cpgrad_mode_gradient(cpgrad_plan_t p, const void* Y, const void* const* A, int n, void* G, int* direction);
+
+/* One sweep of the multiplicative nonnegative update of eq. 2.18 on the bound
+ * tensor, with the gradients from the fast chains of Algorithm 2 in the
+ * Section 4 order (n*, ..., 1, n*+1, ..., N; each mode's gradient uses the
+ * factors updated before it):
+ *   A^(n) <- A^(n) ⊛ G^(n) ⊘ (A^(n) Gamma^(n))
+ * (float64 arithmetic, one rounding to the factor type; a denominator below
+ * the factor type's smallest normal number is raised to it).  Meant for
+ * nonnegative Y and factors, which it keeps nonnegative.  Then the cost of
+ * eq. 2.12 and the fit, as cpals_step (NULL outputs: asynchronous).
+ * Errors: CPG_ERR_INVALID (Y not the bound tensor), CPG_ERR_NONFINITE,
+ * CPG_ERR_HIP. */
+int cpntf_step(cpgrad_plan_t p, const void* Y, void* const* A, double* cost_out, double* fit_out);
+
 /* Allocation-free variant of cpgrad_all_modes, for callers that cannot
  * allocate device memory: code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc.  No plan is created: the shape, types and

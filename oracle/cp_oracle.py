@@ -18,7 +18,7 @@ __all__ = [
     "mttkrp", "cp_gradient_all", "gradient_entry", "n_star", "gram", "gamma",
     "cholesky_jitter_solve", "NotSPD", "als_order", "als_sweep", "cp_als", "cp_full",
     "cost_explicit", "cost_identity", "fit_from_cost", "norm2", "e_gradient_all",
-    "gradient_row",
+    "gradient_row", "ntf_update", "ntf_sweep",
 ]
 
 JITTER = 1e-12
@@ -263,3 +263,36 @@ def cp_als(Y, A, sweeps, tol=None, order=None):
         if tol is not None and len(fits) > 1 and abs(fits[-1] - fits[-2]) < tol:
             break
     return A, fits
+
+
+# ----------------------------------------------------------------------------
+# the multiplicative nonnegative update (eq. 2.18)
+# ----------------------------------------------------------------------------
+
+def ntf_update(G, An, Gam, tiny=np.finfo(np.float64).tiny):
+    """eq. 2.18 for one mode: A^(n) ⊛ G^(n) ⊘ (A^(n) Gamma^(n)); a denominator
+    below ``tiny`` (the factor type's smallest normal number) is raised to it."""
+    den = An @ Gam
+    return An * G / np.maximum(den, tiny)
+
+
+def ntf_sweep(Y, A, order=None, normY2=None, tiny=np.finfo(np.float64).tiny):
+    """One sweep of eq. 2.18, each G^(n) by the definition with the current
+    factors, in the Section 4 order by default (the order in which the fast
+    gradients of Algorithm 2 become available).  Returns ``(A_new, cost, fit)``
+    with the cost by the identity of eq. 2.12, as ``als_sweep``."""
+    N = Y.ndim
+    A = [M.copy() for M in A]
+    if order is None:
+        order = als_order(N, n_star(Y.shape))
+    G_last = None
+    for n in order:
+        G = mttkrp(Y, A, n)
+        A[n] = ntf_update(G, A[n], gamma(A, n), tiny)
+        if n == order[-1]:
+            G_last = G
+    if normY2 is None:
+        normY2 = norm2(Y)
+    grams = [gram(M) for M in A]
+    D = cost_identity(normY2, G_last, A[order[-1]], grams)
+    return A, D, fit_from_cost(D, normY2)

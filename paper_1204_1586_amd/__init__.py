@@ -11,6 +11,7 @@ from ._lib import (  # noqa: F401
 )
 from ._lib import (  # noqa: F401
     CPG_BF16, CPG_F32, CPG_F64, CPG_MODE_BF16, CPG_MODE_BF16_REFINED, CPG_MODE_NATIVE, CPG_OPT_FORCE_NSTAR,
-    CPG_OPT_KERNEL, CPG_OPT_MFMA_COLS, NOALLOC_SCRATCH_BYTES, CPG_OPT_PROFILE, EXPORTS, LIB, LIB_PATH, CpgError, Plan, cp_fit, cpals_step, cpgrad_all_modes, cpgrad_all_modes_noalloc, cpgrad_bind,
+    CPG_OPT_KERNEL, CPG_OPT_MFMA_COLS, NOALLOC_SCRATCH_BYTES, CPG_OPT_PROFILE, EXPORTS, LIB, LIB_PATH, CpgError, Plan, cp_fit, cpals_step, cpgrad_all_modes, cpgrad_all_modes_noalloc, cpgrad_bind, cpgrad_e_gradient,
+    cpgrad_mode_gradient, cpntf_step,
     cpgrad_destroy, cpgrad_last_fit, cpgrad_plan, cpgrad_plan_info, cpgrad_plan_path, cpgrad_profile_read, cpgrad_query, cpgrad_set_option, cpgrad_version,
 )

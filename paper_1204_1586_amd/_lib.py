@@ -33,7 +33,8 @@ EXPORTS = ["cpgrad_plan", "cpgrad_plan_info", "cpgrad_query", "cpgrad_set_option
            "cpgrad_status_string", "cpgrad_version",
            "cpmlp_create", "cpmlp_num_params", "cpmlp_set_params", "cpmlp_get_params", "cpmlp_forward",
            "cpmlp_gradients", "cpmlp_train_step", "cpmlp_destroy", "cpals_features", "cp_fit_extrapolated",
-           "cpals_learned_step", "cpgrad_all_modes_noalloc", "cpgrad_plan_path"]
+           "cpals_learned_step", "cpgrad_all_modes_noalloc", "cpgrad_plan_path", "cpgrad_e_gradient",
+           "cpgrad_mode_gradient", "cpntf_step"]
 NFEAT = 12
 
 
@@ -64,6 +65,10 @@ def _load():
         "cpgrad_all_modes_noalloc": (ctypes.c_int, [ctypes.c_int, i64p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                                      ctypes.c_int, vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]),
         "cpals_step": (ctypes.c_int, [vp, vp, ctypes.POINTER(vp), dp, dp]),
+        "cpntf_step": (ctypes.c_int, [vp, vp, ctypes.POINTER(vp), dp, dp]),
+        "cpgrad_e_gradient": (ctypes.c_int, [vp, vp, ctypes.POINTER(vp), ctypes.POINTER(vp)]),
+        "cpgrad_mode_gradient": (ctypes.c_int, [vp, vp, ctypes.POINTER(vp), ctypes.c_int, vp,
+                                                ctypes.POINTER(ctypes.c_int)]),
         "cp_fit": (ctypes.c_int, [vp, vp, ctypes.POINTER(vp), dp, dp]),
         "cpgrad_last_fit": (ctypes.c_int, [vp, dp, dp]),
         "cpgrad_destroy": (ctypes.c_int, [vp]),
@@ -262,6 +267,45 @@ def cpgrad_all_modes_noalloc(dims, R, Y, A, G, y_dtype="f32", factor_dtype=None,
     _check(LIB.cpgrad_all_modes_noalloc(len(dims), arr, int(R), ydt, fdt, md, ctypes.c_void_p(Y.data_ptr()),
                                         _ptrs(A), _ptrs(G), ctypes.c_void_p(stream.cuda_stream)),
            "cpgrad_all_modes_noalloc")
+
+
+def cpgrad_e_gradient(plan, Y, A, E):
+    """E[n] <- Y_(n)(⊙_{k≠n} A^(k)) - A^(n) Gamma^(n) for all n (eq. 2.13 without -2; asynchronous)."""
+    _check_y(plan, Y)
+    _check_factors(plan, A)
+    _check_factors(plan, E, "E")
+    _check(LIB.cpgrad_e_gradient(plan.handle, ctypes.c_void_p(Y.data_ptr()), _ptrs(A), _ptrs(E)),
+           "cpgrad_e_gradient")
+
+
+def cpgrad_mode_gradient(plan, Y, A, n, G):
+    """G <- Y_(n)(⊙_{k≠n} A^(k)) for one mode n (1-based) by Section 3.2; returns
+    the direction taken (0 right-to-left, 1 left-to-right)."""
+    _check_y(plan, Y)
+    _check_factors(plan, A)
+    if not (1 <= int(n) <= plan.N):
+        raise ValueError(f"mode {n} outside [1, {plan.N}]")
+    if not (isinstance(G, torch.Tensor) and G.is_cuda and G.is_contiguous() and
+            tuple(G.shape) == (plan.dims[n - 1], plan.R) and G.dtype == TORCH_DTYPE[plan.fdt]):
+        raise ValueError(f"G must be a contiguous ({plan.dims[n - 1]}, {plan.R}) {TORCH_DTYPE[plan.fdt]} CUDA tensor")
+    d = ctypes.c_int()
+    _check(LIB.cpgrad_mode_gradient(plan.handle, ctypes.c_void_p(Y.data_ptr()), _ptrs(A), int(n),
+                                    ctypes.c_void_p(G.data_ptr()), ctypes.byref(d)), "cpgrad_mode_gradient")
+    return d.value
+
+
+def cpntf_step(plan, Y, A, sync=True):
+    """One multiplicative nonnegative sweep (eq. 2.18), A updated in place.
+    Returns (cost, fit) if sync, else None."""
+    _check_y(plan, Y)
+    _check_factors(plan, A)
+    if sync:
+        c, f = ctypes.c_double(), ctypes.c_double()
+        _check(LIB.cpntf_step(plan.handle, ctypes.c_void_p(Y.data_ptr()), _ptrs(A), ctypes.byref(c),
+                              ctypes.byref(f)), "cpntf_step")
+        return c.value, f.value
+    _check(LIB.cpntf_step(plan.handle, ctypes.c_void_p(Y.data_ptr()), _ptrs(A), None, None), "cpntf_step")
+    return None
 
 
 def cpals_step(plan, Y, A, sync=True):

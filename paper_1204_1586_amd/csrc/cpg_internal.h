@@ -194,6 +194,14 @@ hipError_t launch_grams(int fdt, const void* facset, double* grams, hipStream_t 
 hipError_t launch_als_update(int fdt, const void* G, void* A, double* grams, int N, int n, int64_t I,
                              int R, int* flags, hipStream_t stream);
 
+// E[n] <- E[n] - A[n] Gamma^(n) for every mode (E[n] holds G^(n) on entry;
+// E is a host array of N device pointers), Gamma^(n) from the float64 Grams.
+hipError_t launch_egrad(int fdt, const void* facset, void* const* E, const double* grams, int N, int64_t max_cells,
+                        hipStream_t stream);
+// eq. 2.18 for mode n: A[n] <- A[n] .* G ./ (A[n] Gamma^(n)); then grams[n] <- A[n]^T A[n].
+hipError_t launch_ntf_update(int fdt, const void* G, void* A, double* grams, int N, int n, int64_t I, int R,
+                             hipStream_t stream);
+
 // ||Y||^2 in float64 -> *out (two-stage, deterministic); scratch >= 1024 doubles
 hipError_t launch_norm2(int ydt, const void* Y, int64_t n, double* scratch, double* out,
                         hipStream_t stream);

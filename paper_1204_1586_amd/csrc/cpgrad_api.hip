@@ -59,6 +59,9 @@ struct cpgrad_plan_s {
     float* l_sigma = nullptr;
     int* l_accept = nullptr;
     int have_prev = 0;
+    // single-mode gradient (Section 3.2): partial buffers of a one-sided pass at another split
+    char* sws = nullptr;
+    size_t sws_bytes = 0;
     // optional HIP-event timing of the big contraction launches
     int profile = 0;
     std::vector<hipEvent_t> ev_start, ev_stop;
@@ -574,46 +577,53 @@ static int run_both_sides(cpgrad_plan_s* p, const FacSet<TC>& fs, void* const* A
     return run_side<TC>(p, fs, 1, A, G, false, false, false);
 }
 
-// Legacy per-kernel chains, used when a gradient does not fit the epilogue's LDS.
-static int right_chain(cpgrad_plan_s* p, const AnyFacSet& fs, void* const* A, void* const* G, bool update) {
+// What a chain does with each gradient it forms: store it, or update that
+// mode's factor from it (eq. 2.14 ALS, or eq. 2.18 multiplicative).
+enum ChainUpdate { kStore = 0, kAls = 1, kNtf = 2 };
+
+static hipError_t chain_update(cpgrad_plan_s* p, int kind, const void* g, void* A, int m) {
+    if (kind == kAls)
+        return launch_als_update(p->fdt, g, A, p->grams, p->N, m, p->dims[m], p->R, p->flags, p->stream);
+    return launch_ntf_update(p->fdt, g, A, p->grams, p->N, m, p->dims[m], p->R, p->stream);
+}
+
+// Per-kernel chains (one launch per step), used when a gradient does not fit
+// the epilogue's LDS and by the multiplicative update.
+static int right_chain(cpgrad_plan_s* p, const AnyFacSet& fs, void* const* A, void* const* G, int update) {
     const void* cur = p->PR;
     int buf = 0;
     for (int n = p->nstar; n >= 1; --n) {          // paper's 1-based mode n
         if (n < p->nstar) {
-            // vec R^(r,n) = reshape(R^(r,n+1), [J_n, I_{n+1}]) a_r^(n+1)   (eq. 3.20)
+            // next chain tensor: contract R^(n+1) with the rank columns of A^(n+1)   (eq. 3.20)
             CPG_TRY(launch_ttv(p->fdt, cur, p->chain[buf], A[n], p->Jn[n], p->dims[n], 1, p->R, p->ld, p->stream));
             cur = p->chain[buf];
             buf ^= 1;
         }
         void* g = update ? p->Gtmp : G[n - 1];
-        // g_r^(n) = reshape(R^(r,n), [J_{n-1}, I_n])^T (a_r^(n-1) (x) ... (x) a_r^(1))   (eq. 3.12)
+        // gradient of mode n from R^(n) and the Khatri-Rao rows of modes 1..n-1   (eq. 3.12)
         CPG_TRY(launch_grad(p->fdt, cur, p->ld, g, fs.ptr(p->fdt), p->Jn[n - 1], p->dims[n - 1], 1, 0, n - 1, 0,
                             0, p->stream));
-        if (update)
-            CPG_TRY(launch_als_update(p->fdt, g, A[n - 1], p->grams, p->N, n - 1, p->dims[n - 1], p->R, p->flags,
-                                      p->stream));
+        if (update) CPG_TRY(chain_update(p, update, g, A[n - 1], n - 1));
     }
     return CPG_OK;
 }
 
-static int left_chain(cpgrad_plan_s* p, const AnyFacSet& fs, void* const* A, void* const* G, bool update) {
+static int left_chain(cpgrad_plan_s* p, const AnyFacSet& fs, void* const* A, void* const* G, int update) {
     const void* cur = p->PL;
     int buf = 0;
     for (int n = p->nstar + 1; n <= p->N; ++n) {
         if (n > p->nstar + 1) {
-            // vec L^(r,n) = reshape(L^(r,n-1), [I_{n-1}, K_{n-1}])^T a_r^(n-1)   (eq. 3.22)
+            // next chain tensor: contract L^(n-1) with the rank columns of A^(n-1)   (eq. 3.22)
             CPG_TRY(launch_ttv(p->fdt, cur, p->chain[buf], A[n - 2], 1, p->dims[n - 2], p->Kn[n - 1], p->R,
                                p->ld, p->stream));
             cur = p->chain[buf];
             buf ^= 1;
         }
         void* g = update ? p->Gtmp : G[n - 1];
-        // g_r^(n) = reshape(L^(r,n), [I_n, K_n]) (a_r^(N) (x) ... (x) a_r^(n+1))   (eq. 3.16)
+        // gradient of mode n from L^(n) and the Khatri-Rao rows of modes n+1..N   (eq. 3.16)
         CPG_TRY(launch_grad(p->fdt, cur, p->ld, g, fs.ptr(p->fdt), 1, p->dims[n - 1], p->Kn[n], 0, 0, n,
                             p->N - n, p->stream));
-        if (update)
-            CPG_TRY(launch_als_update(p->fdt, g, A[n - 1], p->grams, p->N, n - 1, p->dims[n - 1], p->R, p->flags,
-                                      p->stream));
+        if (update) CPG_TRY(chain_update(p, update, g, A[n - 1], n - 1));
     }
     return CPG_OK;
 }
@@ -747,7 +757,7 @@ static int als_sweep_core(cpgrad_plan_s* p, const void* Y, void* const* A) {
                                : run_side<float>(p, fs.f, 0, A, nullptr, true, true, false,
                                                  pre ? (const float*)p->Gtmp : nullptr, pre);
     else
-        st = right_chain(p, fs, A, nullptr, true);
+        st = right_chain(p, fs, A, nullptr, kAls);
     if (st) return st;
     // pass 2 over Y: P_L with the updated A^(1..n*), then modes n*+1, ..., N and the cost
     CPG_TRY(run_contract(p, Y, fs, p->t_left, 2));
@@ -762,7 +772,7 @@ static int als_sweep_core(cpgrad_plan_s* p, const void* Y, void* const* A) {
                                                  pre ? (const float*)p->Gtmp : nullptr);
         if (st) return st;
     } else {
-        st = left_chain(p, fs, A, nullptr, true);
+        st = left_chain(p, fs, A, nullptr, kAls);
         if (st) return st;
         // cost of eq. 2.12: Gtmp holds G^(N) (taken before the A^(N) update)
         CPG_TRY(launch_cost_fit(p->fdt, p->Gtmp, A[p->N - 1], p->dims[p->N - 1], p->R, nullptr, p->grams, p->N,
@@ -873,9 +883,101 @@ static int all_modes_core(cpgrad_plan_s* p, const void* Y, const void* const* A,
         if (pre) return all_modes_tail(p, fs.f, G);
         return run_both_sides<float>(p, fs.f, (void* const*)A, G);
     }
-    st = right_chain(p, fs, (void* const*)A, G, false);
+    st = right_chain(p, fs, (void* const*)A, G, kStore);
     if (st) return st;
-    return left_chain(p, fs, (void* const*)A, G, false);
+    return left_chain(p, fs, (void* const*)A, G, kStore);
+}
+
+// The same tensor viewed at split s (1-based) for one one-sided pass
+// (roles 1: P_R = Y_(1:s) KR(s+1..N), eq. 3.10; roles 2: P_L =
+// KR(1..s)^T Y_(1:s), eq. 3.9), with partial and result buffers from the
+// plan's single-mode workspace (grown on first need).
+static int split_view(cpgrad_plan_s* p, int s, int roles, cpgrad_plan_s* v) {
+    v->N = p->N;
+    v->R = p->R;
+    v->ld = p->ld;
+    for (int n = 0; n < p->N; ++n) {
+        v->dims[n] = p->dims[n];
+        v->fd[n] = p->fd[n];
+    }
+    for (int n = 0; n <= p->N; ++n) {
+        v->Jn[n] = p->Jn[n];
+        v->Kn[n] = p->Kn[n];
+    }
+    v->ydt = p->ydt;
+    v->fdt = p->fdt;
+    v->mode = p->mode;
+    v->stream = p->stream;
+    v->acc = p->acc;
+    v->numel = p->numel;
+    v->kernel_opt = p->kernel_opt;
+    v->opt_cols = p->opt_cols;
+    v->nstar = s;
+    v->J = p->Jn[s];
+    v->K = p->Kn[s];
+    if (plan_kind_ok(v)) return CPG_ERR_UNSUPPORTED;
+    const Tiling t = tile_pass(v, roles);
+    if (roles == 1) v->t_right = t;
+    else v->t_left = t;
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const int64_t rows = roles == 1 ? v->J : v->K, parts = roles == 1 ? t.n_kc : t.n_jr;
+    const size_t res = al((size_t)rows * v->ld * v->acc);
+    const size_t need = res + al((size_t)parts * rows * v->ld * v->acc);
+    if (need > p->sws_bytes) {
+        if (p->sws) (void)hipFree(p->sws);
+        p->sws = nullptr;
+        p->sws_bytes = 0;
+        if (hipMalloc((void**)&p->sws, need) != hipSuccess) {
+            (void)hipGetLastError();
+            p->sws = nullptr;
+            return CPG_ERR_NOMEM;
+        }
+        p->sws_bytes = need;
+    }
+    if (roles == 1) {
+        v->PR = p->sws;
+        v->PRpart = p->sws + res;
+    } else {
+        v->PL = p->sws;
+        v->PLpart = p->sws + res;
+    }
+    v->fused_first = false;
+    return CPG_OK;
+}
+
+// Section 3.2: the gradient of one mode n (1-based) from one pass over Y.
+// Right to left (eqs. 3.10, 3.12: split n, then contract the J_{n-1} leading
+// rows with the Khatri-Rao rows of modes 1..n-1) when J_n <= K_{n-1};
+// left to right (eqs. 3.9, 3.16: split n-1, then contract the K_n trailing
+// columns with the Khatri-Rao rows of modes n+1..N) otherwise.  Mode 1 can
+// only go right to left and mode N only left to right.
+static int mode_gradient_core(cpgrad_plan_s* p, const void* Y, const void* const* A, int n, void* G, int* dir) {
+    const int N = p->N;
+    const bool can_r = n <= N - 1, can_l = n >= 2;
+    bool right = can_r && (!can_l || p->Jn[n] <= p->Kn[n - 1]);
+    cpgrad_plan_s v;
+    int st = split_view(p, right ? n : n - 1, right ? 1 : 2, &v);
+    if (st == CPG_ERR_UNSUPPORTED && (right ? can_l : can_r)) {
+        right = !right;   // the matrix-core kind of a reduced-precision mode cannot take that split
+        st = split_view(p, right ? n : n - 1, right ? 1 : 2, &v);
+    }
+    if (st) return st;
+    const AnyFacSet fs = facsets(&v, A);
+    if (right) {
+        CPG_TRY(run_contract(&v, Y, fs, v.t_right, 1));
+        st = finish_partials(&v, nullptr, v.t_right, 1);
+        if (st) return st;
+        CPG_TRY(launch_grad(v.fdt, v.PR, v.ld, G, fs.ptr(v.fdt), v.Jn[n - 1], v.dims[n - 1], 1, 0, n - 1, 0, 0,
+                            v.stream));
+    } else {
+        CPG_TRY(run_contract(&v, Y, fs, v.t_left, 2));
+        st = finish_partials(&v, nullptr, v.t_left, 2);
+        if (st) return st;
+        CPG_TRY(launch_grad(v.fdt, v.PL, v.ld, G, fs.ptr(v.fdt), 1, v.dims[n - 1], v.Kn[n], 0, 0, n, N - n,
+                            v.stream));
+    }
+    if (dir) *dir = right ? 0 : 1;
+    return CPG_OK;
 }
 
 // Static scratch of the allocation-free entry point: one copy per GPU, held
@@ -1072,6 +1174,57 @@ int cpgrad_all_modes_noalloc(int N, const int64_t* dims, int R, int y_dtype, int
     return all_modes_core(&p, Y, A, G);
 }
 
+int cpgrad_e_gradient(cpgrad_plan_t p, const void* Y, const void* const* A, void* const* E) {
+    if (!p || !Y || !A || !E) return CPG_ERR_INVALID;
+    if (((uintptr_t)Y & 15) != 0) return CPG_ERR_INVALID;
+    for (int n = 0; n < p->N; ++n)
+        if (!A[n] || !E[n]) return CPG_ERR_INVALID;
+    int st = all_modes_core(p, Y, A, E);
+    if (st) return st;
+    const AnyFacSet fs = facsets(p, A);
+    CPG_TRY(launch_grams(p->fdt, fs.ptr(p->fdt), p->grams, p->stream));
+    int64_t maxI = 0;
+    for (int n = 0; n < p->N; ++n) maxI = std::max<int64_t>(maxI, p->dims[n]);
+    CPG_TRY(launch_egrad(p->fdt, fs.ptr(p->fdt), E, p->grams, p->N, maxI * p->R, p->stream));
+    return CPG_OK;
+}
+
+int cpgrad_mode_gradient(cpgrad_plan_t p, const void* Y, const void* const* A, int n, void* G, int* direction) {
+    if (!p || !Y || !A || !G || n < 1 || n > p->N) return CPG_ERR_INVALID;
+    if (((uintptr_t)Y & 15) != 0) return CPG_ERR_INVALID;
+    for (int m = 0; m < p->N; ++m)
+        if (!A[m]) return CPG_ERR_INVALID;
+    return mode_gradient_core(p, Y, A, n, G, direction);
+}
+
+int cpntf_step(cpgrad_plan_t p, const void* Y, void* const* A, double* cost_out, double* fit_out) {
+    if (!p || !Y || !A) return CPG_ERR_INVALID;
+    if (Y != p->bound) return CPG_ERR_INVALID;
+    for (int n = 0; n < p->N; ++n)
+        if (!A[n]) return CPG_ERR_INVALID;
+    const AnyFacSet fs = facsets(p, (const void* const*)A);
+    hipLaunchKernelGGL(k_zero_flags, dim3(1), dim3(64), 0, p->stream, p->flags);
+    CPG_TRY(hipGetLastError());
+    CPG_TRY(launch_grams(p->fdt, fs.ptr(p->fdt), p->grams, p->stream));
+    // pass 1: P_R with the current A^(n*+1..N), then modes n*, ..., 1 (eq. 2.18 after each gradient)
+    CPG_TRY(run_contract(p, Y, fs, p->t_right, 1));
+    int st = finish_partials(p, nullptr, p->t_right, 1);
+    if (st) return st;
+    st = right_chain(p, fs, A, nullptr, kNtf);
+    if (st) return st;
+    // pass 2: P_L with the updated A^(1..n*), then modes n*+1, ..., N
+    CPG_TRY(run_contract(p, Y, fs, p->t_left, 2));
+    st = finish_partials(p, nullptr, p->t_left, 2);
+    if (st) return st;
+    st = left_chain(p, fs, A, nullptr, kNtf);
+    if (st) return st;
+    // cost of eq. 2.12: Gtmp holds G^(N) (taken before the A^(N) update)
+    CPG_TRY(launch_cost_fit(p->fdt, p->Gtmp, A[p->N - 1], p->dims[p->N - 1], p->R, nullptr, p->grams, p->N, p->scal,
+                            p->flags, p->stream));
+    if (!cost_out && !fit_out) return CPG_OK;
+    return readback(p, cost_out, fit_out);
+}
+
 int cpals_step(cpgrad_plan_t p, const void* Y, void* const* A, double* cost_out, double* fit_out) {
     if (!p || !Y || !A) return CPG_ERR_INVALID;
     if (Y != p->bound) return CPG_ERR_INVALID;
@@ -1173,6 +1326,7 @@ int cpgrad_destroy(cpgrad_plan_t p) {
     else (void)hipDeviceSynchronize();
     release(p);
     if (p->lws) (void)hipFree(p->lws);
+    if (p->sws) (void)hipFree(p->sws);
     if (p->host) (void)hipHostFree(p->host);
     for (size_t i = 0; i < p->ev_start.size(); ++i) {
         (void)hipEventDestroy(p->ev_start[i]);
