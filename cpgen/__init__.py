@@ -110,14 +110,15 @@ def noisy_cp_tensor(factors, snr_db, g_noise: np.random.Generator, storage="f64"
 
     The clean tensor is built and the noise added in float64 column chunks of
     the (I_1..I_s) x (I_{s+1}..I_N) view, then cast to the storage type:
-    'f64', 'f32' or 'bf16' (uint16 bit patterns, round to nearest even).
+    'f64', 'f32', 'f16' (round to nearest even) or 'bf16' (uint16 bit
+    patterns, round to nearest even).
     """
     dims = [A.shape[0] for A in factors]
     N = len(dims)
     s = max(1, N // 2)
     J = int(np.prod(dims[:s]))
     K = int(np.prod(dims[s:]))
-    dt = {"f64": np.float64, "f32": np.float32, "bf16": np.uint16}[storage]
+    dt = {"f64": np.float64, "f32": np.float32, "bf16": np.uint16, "f16": np.float16}[storage]
     out = np.empty(J * K, dtype=dt)
     # pass 1: norm of the clean tensor (the chunks are rebuilt in pass 2)
     nrm2 = 0.0

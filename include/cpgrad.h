@@ -34,6 +34,14 @@
  *   F32      F32           BF16_REFINED    + residual terms (hi*lo + lo*hi) in the same pass
  *   BF16     F32           BF16            Y stored bf16, Khatri-Rao tiles bf16
  *   BF16     F32           BF16_REFINED    + Y*KR_lo term (Y is exact in bf16)
+ *   F32      F32           F16_SCALED      fp16 MFMA: each wave's 64 x 32 tile of Y in a step
+ *                                          is scaled by a power of two from its largest
+ *                                          magnitude, each Khatri-Rao column r by a power of
+ *                                          two from prod_m max_i |A^(m)(i,r)| (its exact
+ *                                          largest magnitude); results unscaled exactly
+ *   F32      F32           F16_SCALED_REFINED  + residual terms (hi*lo + lo*hi), same pass
+ *   BF16/F16 F32           F16_SCALED(_REFINED)  Y stored bf16 or fp16 (converts to scaled
+ *                                          fp16 exactly); refinement adds Y*KR_lo
  *   Gram matrices, the normal-equation solve of eq. 2.14, ||Y||^2 and the
  *   cost of eq. 2.12 are float64 in every mode.
  *   The reduced-precision modes run only on the matrix cores: a plan whose
@@ -62,12 +70,14 @@ extern "C" {
 
 typedef struct cpgrad_plan_s* cpgrad_plan_t;
 
-typedef enum { CPG_F64 = 0, CPG_F32 = 1, CPG_BF16 = 2 } cpg_dtype;
+typedef enum { CPG_F64 = 0, CPG_F32 = 1, CPG_BF16 = 2, CPG_F16 = 3 } cpg_dtype;
 
 typedef enum {
-    CPG_MODE_NATIVE = 0,       /* contraction in the tensor's own precision          */
-    CPG_MODE_BF16 = 1,         /* bf16 MFMA, fp32 accumulation, no refinement         */
-    CPG_MODE_BF16_REFINED = 2  /* bf16 MFMA + one residual refinement term, same pass */
+    CPG_MODE_NATIVE = 0,             /* contraction in the tensor's own precision          */
+    CPG_MODE_BF16 = 1,               /* bf16 MFMA, fp32 accumulation, no refinement         */
+    CPG_MODE_BF16_REFINED = 2,       /* bf16 MFMA + one residual refinement term, same pass */
+    CPG_MODE_F16_SCALED = 3,         /* fp16 MFMA on power-of-two scaled tiles, fp32 accum. */
+    CPG_MODE_F16_SCALED_REFINED = 4  /* + the residual refinement terms, same pass          */
 } cpg_mode;
 
 typedef enum {
@@ -118,7 +128,7 @@ int cpgrad_plan_info(cpgrad_plan_t p, int* n_star, size_t* workspace_bytes,
 
 /* Which kernels the plan runs (host query, no device work): the contraction
  * kernel of its passes (1 = generic vector-ALU kernel, 2 = float32 matrix
- * cores, 3 = bf16 matrix cores) and whether the split partials are reduced by
+ * cores, 3 = bf16 matrix cores, 4 = scaled fp16 matrix cores) and whether the split partials are reduced by
  * the fused multi-block reduction (1) or the generic one (0).  Either output
  * pointer may be NULL.  Errors: CPG_ERR_INVALID. */
 int cpgrad_plan_path(cpgrad_plan_t p, int* contraction_kernel, int* fused_reduction);

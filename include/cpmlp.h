@@ -78,6 +78,19 @@ int cpals_features(cpgrad_plan_t p, const void* const* A, const void* const* A_s
 int cp_fit_extrapolated(cpgrad_plan_t p, const void* Y, const void* const* A, const void* const* A_start,
                         double sigma, double* cost_out, double* fit_out);
 
+/* Extrapolation step with a step size the caller chooses (sigma >= 0):
+ * A_ext = A_new + sigma (A_new - A_prev); the exact cost of eq. 2.12 of A_ext
+ * against the bound Y (one pass over Y plus float64 Grams) is compared with
+ * the plan's last cost, which must be the cost of A_new (call this right
+ * after the cpals_step or cp_fit that gave A_new).  Only if it is lower is
+ * A_new overwritten with A_ext (*accepted = 1) and the plan's last cost
+ * replaced; otherwise A_new is unchanged (*accepted = 0).  Returns the cost
+ * and fit of the kept factors.  accepted, cost_out, fit_out may be NULL.
+ * Waits for the stream.  Errors: CPG_ERR_INVALID (NULL, Y not the bound
+ * tensor, sigma negative or not finite), CPG_ERR_NONFINITE, CPG_ERR_HIP. */
+int cpals_extrapolate(cpgrad_plan_t p, const void* Y, void* const* A_new, const void* const* A_prev, double sigma,
+                      int* accepted, double* cost_out, double* fit_out);
+
 /* One learned-extrapolation ALS step on the bound Y: keeps A as A_start,
  * runs cpals_step, forms the features, lets the network propose sigma,
  * evaluates the exact cost of A + sigma (A - A_start) and keeps it only if

@@ -15,8 +15,9 @@ import torch
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libcpgrad.so")
 
-CPG_F64, CPG_F32, CPG_BF16 = 0, 1, 2
+CPG_F64, CPG_F32, CPG_BF16, CPG_F16 = 0, 1, 2, 3
 CPG_MODE_NATIVE, CPG_MODE_BF16, CPG_MODE_BF16_REFINED = 0, 1, 2
+CPG_MODE_F16_SCALED, CPG_MODE_F16_SCALED_REFINED = 3, 4
 CPG_OPT_FORCE_NSTAR, CPG_OPT_KERNEL, CPG_OPT_PROFILE, CPG_OPT_MFMA_COLS = 1, 2, 3, 4
 MAX_MODES, MAX_RANK = 16, 64
 
@@ -24,9 +25,10 @@ STATUS = {0: "CPG_OK", -1: "CPG_ERR_INVALID", -2: "CPG_ERR_NOMEM", -3: "CPG_ERR_
           -5: "CPG_ERR_UNSUPPORTED", -6: "CPG_ERR_NONFINITE", -7: "CPG_ERR_SCRATCH"}
 NOALLOC_SCRATCH_BYTES = 32 << 20
 
-DTYPES = {"f64": CPG_F64, "f32": CPG_F32, "bf16": CPG_BF16}
-MODES = {"native": CPG_MODE_NATIVE, "bf16": CPG_MODE_BF16, "bf16_refined": CPG_MODE_BF16_REFINED}
-TORCH_DTYPE = {CPG_F64: torch.float64, CPG_F32: torch.float32, CPG_BF16: torch.bfloat16}
+DTYPES = {"f64": CPG_F64, "f32": CPG_F32, "bf16": CPG_BF16, "f16": CPG_F16}
+MODES = {"native": CPG_MODE_NATIVE, "bf16": CPG_MODE_BF16, "bf16_refined": CPG_MODE_BF16_REFINED,
+         "f16_scaled": CPG_MODE_F16_SCALED, "f16_scaled_refined": CPG_MODE_F16_SCALED_REFINED}
+TORCH_DTYPE = {CPG_F64: torch.float64, CPG_F32: torch.float32, CPG_BF16: torch.bfloat16, CPG_F16: torch.float16}
 
 EXPORTS = ["cpgrad_plan", "cpgrad_plan_info", "cpgrad_query", "cpgrad_set_option", "cpgrad_profile_read",
            "cpgrad_bind", "cpgrad_all_modes", "cpals_step", "cp_fit", "cpgrad_last_fit", "cpgrad_destroy",
@@ -34,7 +36,7 @@ EXPORTS = ["cpgrad_plan", "cpgrad_plan_info", "cpgrad_query", "cpgrad_set_option
            "cpmlp_create", "cpmlp_num_params", "cpmlp_set_params", "cpmlp_get_params", "cpmlp_forward",
            "cpmlp_gradients", "cpmlp_train_step", "cpmlp_destroy", "cpals_features", "cp_fit_extrapolated",
            "cpals_learned_step", "cpgrad_all_modes_noalloc", "cpgrad_plan_path", "cpgrad_e_gradient",
-           "cpgrad_mode_gradient", "cpntf_step"]
+           "cpgrad_mode_gradient", "cpntf_step", "cpals_extrapolate"]
 NFEAT = 12
 
 
@@ -86,6 +88,8 @@ def _load():
                                           ctypes.c_float, ctypes.c_int, vp]),
         "cp_fit_extrapolated": (ctypes.c_int, [vp, vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_double, dp,
                                                dp]),
+        "cpals_extrapolate": (ctypes.c_int, [vp, vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_double,
+                                             ctypes.POINTER(ctypes.c_int), dp, dp]),
         "cpals_learned_step": (ctypes.c_int, [vp, vp, vp, ctypes.POINTER(vp), dp, ctypes.c_int, ctypes.c_int,
                                               ctypes.c_float, ctypes.c_int, dp, dp, ctypes.POINTER(ctypes.c_int),
                                               ctypes.POINTER(ctypes.c_float)]),
@@ -453,6 +457,19 @@ def cp_fit_extrapolated(plan, Y, A, A_start, sigma):
     _check(LIB.cp_fit_extrapolated(plan.handle, ctypes.c_void_p(Y.data_ptr()), _ptrs(A), _ptrs(A_start),
                                    float(sigma), ctypes.byref(c), ctypes.byref(f)), "cp_fit_extrapolated")
     return c.value, f.value
+
+
+def cpals_extrapolate(plan, Y, A_new, A_prev, sigma):
+    """Keep A_new + sigma (A_new - A_prev) in A_new only if its exact cost is
+    below the plan's last cost (that of A_new); returns (cost, fit, accepted)."""
+    _check_y(plan, Y)
+    _check_factors(plan, A_new, "A_new")
+    _check_factors(plan, A_prev, "A_prev")
+    c, f, acc = ctypes.c_double(), ctypes.c_double(), ctypes.c_int()
+    _check(LIB.cpals_extrapolate(plan.handle, ctypes.c_void_p(Y.data_ptr()), _ptrs(A_new), _ptrs(A_prev),
+                                 float(sigma), ctypes.byref(acc), ctypes.byref(c), ctypes.byref(f)),
+           "cpals_extrapolate")
+    return c.value, f.value, acc.value
 
 
 def cpals_learned_step(plan, mlp, Y, A, costs, iteration, last_sigma, last_accept):

@@ -83,7 +83,7 @@ hipError_t launch_epi_rows(const EpiRows& a, hipStream_t stream);
 
 // Tiling of one contraction pass over the J x K view Y_(1:n*).
 struct Tiling {
-    int kernel;        // 1 = generic vector ALU, 2 = float32 MFMA, 3 = bf16 MFMA
+    int kernel;        // 1 = generic vector ALU, 2 = float32 MFMA, 3 = bf16 MFMA, 4 = scaled fp16 MFMA
     int rt;            // rank tile (padded rank) used by the kernel
     int jtb;           // j-tiles (of 64 rows, or the MFMA kernel's row tile) per block
     int64_t ktb;       // k-tiles (of 64 columns) per block
@@ -130,12 +130,13 @@ inline int64_t fac_stage_floats(int N, const int64_t* dims, int R) {
 }
 hipError_t launch_contract_mfma(int ydt, int mode, const void* Y, int64_t J, int64_t K, const Tiling& t,
                                 int roles, const MfmaBufs& bufs, hipStream_t stream);
+// 16-bit matrix-core contraction: bf16 modes (kind 3) and the scaled fp16 modes (kind 4)
 hipError_t launch_contract_bf16(int ydt, int mode, const void* Y, int64_t J, int64_t K, const Tiling& t,
                                 int roles, const MfmaBufs& bufs, hipStream_t stream);
 bool mfma_supported(int ydt, int fdt, int mode, int R);
 // widest column chunk (a multiple of 32) the float32 / bf16 MFMA kernels hold in LDS
 int64_t mfma_f32_max_cols(int rt, int roles, int64_t fac_stage = 0);
-int64_t mfma_bf16_max_cols(int rt, int roles, bool ylo, bool klo);
+int64_t mfma_bf16_max_cols(int rt, int roles, bool ylo, bool klo, bool f16);
 
 // One side of the fused partial reduction (float32): output row i of a side is
 //   G(i, r) = sum_t Z(row(i, t), r) KR(t, r),  Z = sum_p parts[p]  (float64, p in order)

@@ -121,7 +121,8 @@ static Tiling tile_mfma(int64_t J, int64_t K, int R, int roles, int kernel, int6
     t.ktb = cols > 0 ? cdiv(cols, 32) : std::max<int64_t>(1, cdiv(steps * t.n_jr, target));
     // LDS holds the KR_R rows of a block's steps
     if (kernel == 2) t.ktb = std::min<int64_t>(t.ktb, mfma_f32_max_cols(t.rt, roles, fac_stage) / 32);
-    if (kernel == 3) t.ktb = std::min<int64_t>(t.ktb, mfma_bf16_max_cols(t.rt, roles, ylo, klo) / 32);
+    if (kernel == 3 || kernel == 4)
+        t.ktb = std::min<int64_t>(t.ktb, mfma_bf16_max_cols(t.rt, roles, ylo, klo, kernel == 4) / 32);
     t.ktb = std::max<int64_t>(1, t.ktb);
     t.n_kc = cdiv(steps, t.ktb);
     return t;
@@ -131,10 +132,13 @@ static Tiling tile_mfma(int64_t J, int64_t K, int R, int roles, int kernel, int6
 // offsets (a 32-column step of Y below 2 GiB), row and column indices that
 // the kernels unravel by 32-bit multiply-shift division (below 2^31), and a
 // grid whose column dimension stays within 65535 blocks.
+static bool refined_mode(int mode) { return mode == CPG_MODE_BF16_REFINED || mode == CPG_MODE_F16_SCALED_REFINED; }
+static bool f16_mode(int mode) { return mode == CPG_MODE_F16_SCALED || mode == CPG_MODE_F16_SCALED_REFINED; }
+
 static bool mfma_shape_ok(const cpgrad_plan_s* p, int kind) {
     const int64_t lim = int64_t(1) << 31;
     if (p->J * 4 * 32 >= lim || p->J >= lim || p->K >= lim) return false;
-    const bool klo = p->mode == CPG_MODE_BF16_REFINED;
+    const bool klo = refined_mode(p->mode);
     for (int roles = 1; roles <= 3; ++roles) {
         const Tiling t = tile_mfma(p->J, p->K, p->R, roles, kind, p->opt_cols, klo && p->ydt == CPG_F32, klo,
                                    fac_stage_floats(p->N, p->dims, p->R));
@@ -144,13 +148,15 @@ static bool mfma_shape_ok(const cpgrad_plan_s* p, int kind) {
 }
 
 // The matrix-core kind a plan's types and mode ask for: 2 = float32 MFMA
-// (native float32), 3 = bf16 MFMA (the bf16 modes), 0 = none (float64).
+// (native float32), 3 = bf16 MFMA (the bf16 modes), 4 = scaled fp16 MFMA (the
+// fp16 modes), 0 = none (float64).
 static int wanted_kind(const cpgrad_plan_s* p) {
+    if (f16_mode(p->mode)) return 4;
     if (p->mode != CPG_MODE_NATIVE) return 3;
     return (p->ydt == CPG_F32 && p->fdt == CPG_F32) ? 2 : 0;
 }
 
-// 0 = generic kernel, 2 = float32 MFMA, 3 = bf16 MFMA (reduced-precision modes).
+// 0 = generic kernel, 2 = float32 MFMA, 3 / 4 = 16-bit MFMA (reduced-precision modes).
 // The native float32 form falls back to the generic kernel (same precision)
 // when the matrix cores cannot take the shape; a reduced-precision mode never
 // does (plan_kind_ok refuses the plan instead).
@@ -162,13 +168,14 @@ static int mfma_kind(const cpgrad_plan_s* p) {
     return kind;
 }
 
-// A plan whose mode or forced kernel cannot be honoured is refused: the bf16
-// modes need the bf16 matrix cores (J a multiple of 8 and a shape they can
-// take), CPG_OPT_KERNEL = 2 needs a matrix-core kind, and the reduced-precision
-// modes cannot be forced onto the generic (full-precision) kernel.
+// A plan whose mode or forced kernel cannot be honoured is refused: the
+// reduced-precision modes need their 16-bit matrix cores (J a multiple of 8
+// and a shape they can take), CPG_OPT_KERNEL = 2 needs a matrix-core kind,
+// and the reduced-precision modes cannot be forced onto the generic
+// (full-precision) kernel.
 static int plan_kind_ok(const cpgrad_plan_s* p) {
     const int kind = mfma_kind(p);
-    if (p->mode != CPG_MODE_NATIVE && kind != 3) return CPG_ERR_UNSUPPORTED;
+    if (p->mode != CPG_MODE_NATIVE && kind != wanted_kind(p)) return CPG_ERR_UNSUPPORTED;
     if (p->kernel_opt == 2 && kind == 0) return CPG_ERR_UNSUPPORTED;
     return CPG_OK;
 }
@@ -176,7 +183,7 @@ static int plan_kind_ok(const cpgrad_plan_s* p) {
 static Tiling tile_pass(const cpgrad_plan_s* p, int roles) {
     const int kind = mfma_kind(p);
     if (kind) {
-        const bool klo = p->mode == CPG_MODE_BF16_REFINED;
+        const bool klo = refined_mode(p->mode);
         return tile_mfma(p->J, p->K, p->R, roles, kind, p->opt_cols, klo && p->ydt == CPG_F32, klo,
                          fac_stage_floats(p->N, p->dims, p->R));
     }
@@ -309,10 +316,10 @@ static KrGen kr_gen(const cpgrad_plan_s* p, const FacSet<float>& fs) {
 static hipError_t launch_contract(cpgrad_plan_s* p, const void* Y, const AnyFacSet& fs, const Tiling& t,
                                   int roles, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr) {
     if (t.n_kc > 65535) return hipErrorInvalidConfiguration;
-    if (t.kernel == 2 || t.kernel == 3) {
+    if (t.kernel >= 2) {
         MfmaBufs o{(float*)p->PRpart, (float*)p->PLpart, p->ld, kr_gen(p, fs.f), ev0, ev1,
                    (int)fac_stage_floats(p->N, p->dims, p->R)};
-        if (t.kernel == 3)
+        if (t.kernel >= 3)
             return launch_contract_bf16(p->ydt, p->mode, Y, p->J, p->K, t, roles, o, p->stream);
         return launch_contract_mfma(p->ydt, p->mode, Y, p->J, p->K, t, roles, o, p->stream);
     }
@@ -338,7 +345,7 @@ static hipError_t run_contract(cpgrad_plan_s* p, const void* Y, const AnyFacSet&
     }
     const size_t i = p->ev_used++;
     p->ev_roles[i] = roles;
-    if (t.kernel == 2 || t.kernel == 3)   // events attached to the kernel launch itself
+    if (t.kernel >= 2)   // events attached to the kernel launch itself
         return launch_contract(p, Y, fs, t, roles, p->ev_start[i], p->ev_stop[i]);
     hipError_t e = hipEventRecord(p->ev_start[i], p->stream);
     if (e != hipSuccess) return e;
@@ -434,7 +441,7 @@ static bool epilogue_fits(const cpgrad_plan_s* p) {
 // both sides walked by the single-block epilogue.
 static bool fused_first_ok(const cpgrad_plan_s* p) {
     const int kind = mfma_kind(p);
-    return (kind == 2 || kind == 3) && p->fdt == CPG_F32 && epilogue_fits(p) && side_first_small(p, 0, 4) &&
+    return kind >= 2 && p->fdt == CPG_F32 && epilogue_fits(p) && side_first_small(p, 0, 4) &&
            side_first_small(p, 1, 4);
 }
 
@@ -838,15 +845,16 @@ static int plan_init(cpgrad_plan_s* p, int N, const int64_t* dims, int R, int y_
     }
     int64_t total = 1;
     for (int n = 0; n < N; ++n) total *= dims[n];
-    if (y_dtype < CPG_F64 || y_dtype > CPG_BF16 || factor_dtype < CPG_F64 || factor_dtype > CPG_BF16 ||
-        mode < CPG_MODE_NATIVE || mode > CPG_MODE_BF16_REFINED)
+    if (y_dtype < CPG_F64 || y_dtype > CPG_F16 || factor_dtype < CPG_F64 || factor_dtype > CPG_F16 ||
+        mode < CPG_MODE_NATIVE || mode > CPG_MODE_F16_SCALED_REFINED)
         return CPG_ERR_INVALID;
     // supported combinations (see the header)
     const bool f64 = (y_dtype == CPG_F64 && factor_dtype == CPG_F64 && mode == CPG_MODE_NATIVE);
     const bool f32 = (y_dtype == CPG_F32 && factor_dtype == CPG_F32);
     const bool b16 = (y_dtype == CPG_BF16 && factor_dtype == CPG_F32 && mode != CPG_MODE_NATIVE);
-    if (!(f64 || f32 || b16)) return CPG_ERR_UNSUPPORTED;
-    if (factor_dtype == CPG_BF16) return CPG_ERR_UNSUPPORTED;
+    const bool h16 = (y_dtype == CPG_F16 && factor_dtype == CPG_F32 && f16_mode(mode));
+    if (!(f64 || f32 || b16 || h16)) return CPG_ERR_UNSUPPORTED;
+    if (factor_dtype == CPG_BF16 || factor_dtype == CPG_F16) return CPG_ERR_UNSUPPORTED;
     p->N = N;
     p->R = R;
     p->ld = 4 * ((R + 3) / 4);
@@ -1057,7 +1065,7 @@ int cpgrad_query(int N, const int64_t* dims, int R, int y_dtype, int factor_dtyp
                  double* alg_flops_all_modes, double* alg_bytes_all_modes) {
     const int st = check_shape(N, dims, R);
     if (st) return st;
-    if (y_dtype < CPG_F64 || y_dtype > CPG_BF16 || factor_dtype < CPG_F64 || factor_dtype > CPG_F32)
+    if (y_dtype < CPG_F64 || y_dtype > CPG_F16 || factor_dtype < CPG_F64 || factor_dtype > CPG_F32)
         return CPG_ERR_INVALID;
     if (force_nstar != 0 && (force_nstar < 1 || force_nstar > N - 1)) return CPG_ERR_INVALID;
     const int ns = force_nstar ? force_nstar : default_nstar(N, dims);
@@ -1278,6 +1286,29 @@ int cp_fit_extrapolated(cpgrad_plan_t p, const void* Y, const void* const* A, co
     st = fit_core(p, Y, e, 2);
     if (st) return st;
     return readback(p, cost_out, fit_out);
+}
+
+int cpals_extrapolate(cpgrad_plan_t p, const void* Y, void* const* A_new, const void* const* A_prev, double sigma,
+                      int* accepted, double* cost_out, double* fit_out) {
+    if (!p || !Y || !A_new || !A_prev || !(sigma >= 0.0) || !std::isfinite(sigma)) return CPG_ERR_INVALID;
+    if (Y != p->bound) return CPG_ERR_INVALID;
+    for (int n = 0; n < p->N; ++n)
+        if (!A_new[n] || !A_prev[n]) return CPG_ERR_INVALID;
+    int st = ensure_learn(p);
+    if (st) return st;
+    const AnyFacSet a = facsets(p, (const void* const*)A_new), s0 = facsets(p, A_prev),
+                    e = plan_facset(p, p->l_ext);
+    CPG_TRY(launch_extrapolate(p->fdt, e.ptr(p->fdt), a.ptr(p->fdt), s0.ptr(p->fdt), nullptr, sigma, p->stream));
+    st = fit_core(p, Y, e, 8);      // exact cost of the extrapolated factors in scal[8]
+    if (st) return st;
+    CPG_TRY(launch_accept(p->fdt, a.ptr(p->fdt), e.ptr(p->fdt), p->scal, p->l_accept, p->stream));
+    if (hipMemcpyAsync(p->host + 11, p->l_accept, sizeof(int), hipMemcpyDeviceToHost, p->stream) != hipSuccess)
+        return CPG_ERR_HIP;
+    st = readback(p, cost_out, fit_out);   // waits for the stream
+    int acc = 0;
+    std::memcpy(&acc, p->host + 11, sizeof(int));
+    if (accepted) *accepted = acc;
+    return st;
 }
 
 int cpals_learned_step(cpgrad_plan_t p, cpmlp_t m, const void* Y, void* const* A, const double* costs, int ncost,

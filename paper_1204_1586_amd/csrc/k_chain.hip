@@ -530,8 +530,12 @@ constexpr int kRedBlocks = 1024;
 template <typename TY>
 __device__ __forceinline__ double yval(const TY* p, int64_t e) { return (double)p[e]; }
 template <>
-__device__ __forceinline__ double yval<uint16_t>(const uint16_t* p, int64_t e) {
+__device__ __forceinline__ double yval<uint16_t>(const uint16_t* p, int64_t e) {   // bf16 bits
     return (double)__uint_as_float(((uint32_t)p[e]) << 16);
+}
+template <>
+__device__ __forceinline__ double yval<_Float16>(const _Float16* p, int64_t e) {
+    return (double)(float)p[e];
 }
 
 template <typename TY>
@@ -561,6 +565,9 @@ hipError_t launch_norm2(int ydt, const void* Y, int64_t n, double* scratch, doub
         hipLaunchKernelGGL(k_norm2_stage1<double>, dim3(kRedBlocks), dim3(256), 0, s, (const double*)Y, n, scratch);
     else if (ydt == CPG_F32)
         hipLaunchKernelGGL(k_norm2_stage1<float>, dim3(kRedBlocks), dim3(256), 0, s, (const float*)Y, n, scratch);
+    else if (ydt == CPG_F16)
+        hipLaunchKernelGGL(k_norm2_stage1<_Float16>, dim3(kRedBlocks), dim3(256), 0, s, (const _Float16*)Y, n,
+                           scratch);
     else
         hipLaunchKernelGGL(k_norm2_stage1<uint16_t>, dim3(kRedBlocks), dim3(256), 0, s, (const uint16_t*)Y, n,
                            scratch);

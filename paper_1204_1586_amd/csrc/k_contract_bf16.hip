@@ -1,6 +1,6 @@
-// Reduced-precision form of the big contraction of Algorithm 2 (steps 4 and
-// 7): both partial products of Y_(1:n*) against Khatri-Rao blocks on bf16
-// matrix cores (v_mfma_f32_16x16x32_bf16) with float32 accumulation.
+// Reduced-precision forms of the big contraction of Algorithm 2 (steps 4 and
+// 7): both partial products of Y_(1:n*) against Khatri-Rao blocks on 16-bit
+// matrix cores (v_mfma_f32_16x16x32_bf16 / _f16) with float32 accumulation.
 //
 //   BF16          : P = bf16(Y) * bf16(KR)
 //   BF16_REFINED  : Y stored as bf16 (exact):  P = Y*KR_hi + Y*KR_lo
@@ -8,6 +8,20 @@
 // with x_hi = bf16(x) and x_lo = bf16(x - x_hi) (round to nearest even); the
 // refinement terms are formed in the same pass over Y, so the bytes moved do
 // not change.  bf16 keeps float32's exponent range, so no scaling is needed.
+//
+//   F16_SCALED(_REFINED): the same products in fp16 (11-bit significand, so
+//   hi + lo carries 22 bits) with power-of-two scaling, since fp16's range is
+//   narrow.  Each wave scales its 64 x 32 tile of Y in a step by 2^e so that
+//   the tile's largest magnitude lands in [2^14, 2^15) (the max is taken over
+//   the loaded tile, so no extra pass over Y is needed and any split works);
+//   each Khatri-Rao column r is scaled by 2^f_r so that its largest magnitude
+//   lands in the same range: that maximum is exactly the product over the
+//   side's modes of max_i |A^(m)(i, r)| (the column is a Kronecker product of
+//   the factor columns), taken by every block from the factors.  Products
+//   accumulate in float32 and are unscaled exactly (powers of two): per step
+//   for the Y scale, at the store for the Khatri-Rao scale.  Y stored as bf16
+//   or fp16 converts to scaled fp16 exactly (over 29 binades below the
+//   tile's maximum), so only float32 Y has a Y_lo term.
 //
 // Block = 4 waves x 64 rows of Y, steps of 32 columns dealt round-robin over
 // the block columns (the grid sweeps Y as one moving window).  Each lane
@@ -35,6 +49,7 @@ namespace cpg {
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef unsigned short v8us __attribute__((ext_vector_type(8)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 
 constexpr int kB16Rows = 256;
 constexpr int kB16Step = 32;
@@ -58,6 +73,42 @@ __device__ __forceinline__ void lds_block_sync_b() {
 }
 
 __device__ __forceinline__ v8bf as_bf(v8us u) { return __builtin_bit_cast(v8bf, u); }
+__device__ __forceinline__ v8h as_h(v8us u) { return __builtin_bit_cast(v8h, u); }
+
+// float <-> fp16 bits (hardware conversion, round to nearest even)
+__device__ __forceinline__ unsigned short f16_bits(float x) { return __builtin_bit_cast(unsigned short, (_Float16)x); }
+__device__ __forceinline__ float f16_to_f(unsigned short b) { return (float)__builtin_bit_cast(_Float16, b); }
+
+// Scaled fp16 operands: a magnitude m is scaled by 2^(kF16Target - floor(log2 m)),
+// landing in [2^14, 2^15) (one binade below fp16's largest finite value).
+constexpr int kF16Target = 14;
+__device__ __forceinline__ int ilog2f(float m) { return (int)((__float_as_uint(m) >> 23) & 0xff) - 127; }
+__device__ __forceinline__ int clamp_exp(int e) { return e < -126 ? -126 : (e > 126 ? 126 : e); }
+__device__ __forceinline__ float pow2f(int e) { return __uint_as_float((uint32_t)(e + 127) << 23); }   // |e| <= 126
+
+// Largest value over the wave (unsigned compare; the callers pass |x| bits).
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+    v = max(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, true));    // quad [1,0,3,2]
+    v = max(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, true));    // quad [2,3,0,1]
+    v = max(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, true));   // half-row mirror
+    v = max(v, (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xF, 0xF, true));   // row mirror
+    const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)v, 0), b = (uint32_t)__builtin_amdgcn_readlane((int)v, 16);
+    const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)v, 32), d = (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
+    return max(max(a, b), max(c, d));
+}
+
+// 16 x 16 x 32 matrix-core product of 8-element operands (bf16 or fp16 bits).
+template <bool F16>
+__device__ __forceinline__ v4f mma16(v8us a, v8us b, v4f c) {
+    if constexpr (F16) return __builtin_amdgcn_mfma_f32_16x16x32_f16(as_h(a), as_h(b), c, 0, 0, 0);
+    else return __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(a), as_bf(b), c, 0, 0, 0);
+}
+
+// 16-bit split of a float32 value: hi = round(x), lo = round(x - hi)
+template <bool F16>
+__device__ __forceinline__ unsigned short to16(float x) { return F16 ? f16_bits(x) : bf16_rne(x); }
+template <bool F16>
+__device__ __forceinline__ float from16(unsigned short b) { return F16 ? f16_to_f(b) : bf16_to_f(b); }
 
 // one step of Y as loaded: float32 storage (two float4 per chunk) or bf16 storage
 struct RawF {
@@ -78,11 +129,13 @@ struct RawSel<false> {
 // LDS row stride (bf16 elements) of the KR_R tile for kcols columns
 __host__ __device__ constexpr int64_t krr_stride(int64_t kcols) { return kcols + 8; }
 
-// TYF: true if Y is stored as float32 (hi/lo split in registers), false for bf16 storage.
-template <bool TYF, int NRT, bool DO_R, bool DO_L, bool REFINE>
+// YK: storage of Y, 0 = float32 (hi/lo split in registers), 1 = bf16, 2 = fp16.
+// F16: fp16 matrix cores with the power-of-two scaling, else bf16.
+template <int YK, int NRT, bool DO_R, bool DO_L, bool REFINE, bool F16>
 __global__ __launch_bounds__(256) void k_contract_bf16(const void* __restrict__ Yv, int64_t J, int64_t K,
                                                         int64_t kcols, int ld, KrGen kg, float* __restrict__ PRpart,
                                                         float* __restrict__ PLpart) {
+    constexpr bool TYF = YK == 0;
     constexpr int RT = NRT * 16;
     constexpr bool YLO = TYF && REFINE;   // a Y_lo term exists
     constexpr bool KLO = REFINE;          // a KR_lo term exists
@@ -92,6 +145,10 @@ __global__ __launch_bounds__(256) void k_contract_bf16(const void* __restrict__ 
     extern __shared__ __attribute__((aligned(16))) unsigned short sKRdyn[];
     __shared__ __attribute__((aligned(16))) unsigned short sTr[DO_R ? 4 : 1][YLO ? 2 : 1][DO_R ? 64 * kTrLd : 8];
     __shared__ v4f sRed[DO_L ? 2 : 1][DO_L ? 4 * 2 * NRT * 64 : 1];
+    // fp16 scaling: factor column maxima (|x| bits) and the Khatri-Rao column
+    // scales: [0] left side, [1] right side, [2] / [3] their inverses
+    __shared__ unsigned int sCm[F16 ? CPG_MAX_MODES : 1][F16 ? RT : 1];
+    __shared__ float sKs[F16 ? 4 : 1][F16 ? RT : 1];
     const int KRS = (int)krr_stride(kcols);
     unsigned short* sKRh = sKRdyn;
     unsigned short* sKRl = sKRdyn + RT * KRS;
@@ -128,22 +185,53 @@ __global__ __launch_bounds__(256) void k_contract_bf16(const void* __restrict__ 
             }
         }
     };
-    // hi / lo split with the hardware conversion (round to nearest even)
-    auto split = [&](const Raw& r, v8us (&hi)[4], v8us (&lo)[4]) {
+    // hi / lo split with the hardware conversion (round to nearest even).
+    // fp16: the wave's tile is first scaled by 2^e from its largest magnitude;
+    // returns the inverse scale (1 for bf16).
+    auto split = [&](const Raw& r, v8us (&hi)[4], v8us (&lo)[4]) -> float {
+        if constexpr (!F16) {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            if constexpr (TYF) {
-                const float x[8] = {r.a[s][0], r.a[s][1], r.a[s][2], r.a[s][3],
-                                    r.b[s][0], r.b[s][1], r.b[s][2], r.b[s][3]};
+            for (int s = 0; s < 4; ++s) {
+                if constexpr (TYF) {
+                    const float x[8] = {r.a[s][0], r.a[s][1], r.a[s][2], r.a[s][3],
+                                        r.b[s][0], r.b[s][1], r.b[s][2], r.b[s][3]};
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) {
+                        const __bf16 h = (__bf16)x[t];
+                        hi[s][t] = __builtin_bit_cast(unsigned short, h);
+                        if (YLO) lo[s][t] = __builtin_bit_cast(unsigned short, (__bf16)(x[t] - (float)h));
+                    }
+                } else {
+                    hi[s] = r.c[s];
+                }
+            }
+            return 1.f;
+        } else {
+            float x[4][8];
+            uint32_t m = 0;
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
 #pragma unroll
                 for (int t = 0; t < 8; ++t) {
-                    const __bf16 h = (__bf16)x[t];
-                    hi[s][t] = __builtin_bit_cast(unsigned short, h);
-                    if (YLO) lo[s][t] = __builtin_bit_cast(unsigned short, (__bf16)(x[t] - (float)h));
+                    if constexpr (TYF) x[s][t] = t < 4 ? r.a[s][t] : r.b[s][t - 4];
+                    else if constexpr (YK == 1) x[s][t] = bf16_to_f(r.c[s][t]);
+                    else x[s][t] = f16_to_f(r.c[s][t]);
+                    m = max(m, __float_as_uint(x[s][t]) & 0x7fffffffu);
                 }
-            } else {
-                hi[s] = r.c[s];
-            }
+            m = wave_max_u32(m);
+            // an all-zero tile keeps scale 1; a non-finite one too (its products stay non-finite)
+            const int e = (m == 0u || m >= 0x7f800000u) ? 0 : clamp_exp(kF16Target - ilog2f(__uint_as_float(m)));
+            const float sc = pow2f(e);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    const float v = x[s][t] * sc;
+                    const unsigned short h = f16_bits(v);
+                    hi[s][t] = h;
+                    if (YLO) lo[s][t] = f16_bits(v - f16_to_f(h));
+                }
+            return pow2f(-e);
         }
     };
 
@@ -263,10 +351,11 @@ __global__ __launch_bounds__(256) void k_contract_bf16(const void* __restrict__ 
                 for (int rt = 0; rt < NRT; ++rt)
 #pragma unroll
                     for (int tt = 0; tt < 8; ++tt) {
-                        const float v = fl[rt][8 * jc + tt];
-                        const unsigned short h = bf16_rne(v);
+                        const float v = fl[rt][8 * jc + tt] * (F16 ? sKs[0][F16 ? rt * 16 + c16 : 0] : 1.f);
+                        const unsigned short h = to16<F16>(v);
                         krl_hi[jc][rt][tt] = h;
-                        if (KLO) krl_lo[DO_L && KLO ? jc : 0][DO_L && KLO ? rt : 0][tt] = bf16_rne(v - bf16_to_f(h));
+                        if (KLO)
+                            krl_lo[DO_L && KLO ? jc : 0][DO_L && KLO ? rt : 0][tt] = to16<F16>(v - from16<F16>(h));
                     }
         }
         if (DO_R) {
@@ -277,9 +366,10 @@ __global__ __launch_bounds__(256) void k_contract_bf16(const void* __restrict__ 
                     const int kk = e / (RT / 4);
 #pragma unroll
                     for (int c = 0; c < 4; ++c) {
-                        const unsigned short h = bf16_rne(t[u][c]);
+                        const float v = t[u][c] * (F16 ? sKs[1][F16 ? r4[u] + c : 0] : 1.f);
+                        const unsigned short h = to16<F16>(v);
                         sKRh[(r4[u] + c) * KRS + kk] = h;
-                        if (KLO) sKRl[(r4[u] + c) * KRS + kk] = bf16_rne(t[u][c] - bf16_to_f(h));
+                        if (KLO) sKRl[(r4[u] + c) * KRS + kk] = to16<F16>(v - from16<F16>(h));
                     }
                 }
             }
@@ -297,7 +387,8 @@ __global__ __launch_bounds__(256) void k_contract_bf16(const void* __restrict__ 
         load_step(nxtRaw, st + kB16Depth);
         __builtin_amdgcn_sched_barrier(0);   // keep the prefetch ahead of the step's MFMAs
         v8us cur_hi[4], cur_lo[4];
-        split(curRaw, cur_hi, cur_lo);
+        const float inv_s = split(curRaw, cur_hi, cur_lo);
+        (void)inv_s;
         if (DO_R) {
             // transpose through this wave's LDS tile: row (32*jc + 8q + t), column (16*kt + c16)
             // Lanes of adjacent columns (c16 even / odd) swap half of their eight
@@ -339,15 +430,16 @@ __global__ __launch_bounds__(256) void k_contract_bf16(const void* __restrict__ 
 #pragma unroll
                 for (int rr = 0; rr < 4; ++rr) {
                     const v8us ah = *(const v8us*)(&sTr[w][0][(16 * rr + c16) * kTrLd + 8 * q]);
-                    accR[rr][rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(ah), as_bf(bh), accR[rr][rt], 0, 0, 0);
-                    if (KLO)
-                        accR[rr][rt] =
-                            __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(ah), as_bf(bl), accR[rr][rt], 0, 0, 0);
+                    // fp16: the step's products in their own accumulator, unscaled by the tile's scale
+                    v4f a = F16 ? v4f{0.f, 0.f, 0.f, 0.f} : accR[rr][rt];
+                    a = mma16<F16>(ah, bh, a);
+                    if (KLO) a = mma16<F16>(ah, bl, a);
                     if (YLO) {
                         const v8us al = *(const v8us*)(&sTr[w][YLO ? 1 : 0][(16 * rr + c16) * kTrLd + 8 * q]);
-                        accR[rr][rt] =
-                            __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(al), as_bf(bh), accR[rr][rt], 0, 0, 0);
+                        a = mma16<F16>(al, bh, a);
                     }
+                    if constexpr (F16) accR[rr][rt] += a * inv_s;
+                    else accR[rr][rt] = a;
                 }
             }
         }
@@ -362,13 +454,12 @@ __global__ __launch_bounds__(256) void k_contract_bf16(const void* __restrict__ 
 #pragma unroll
                     for (int jc = 0; jc < 2; ++jc) {
                         const int s = 2 * jc + kt;
-                        a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(cur_hi[s]), as_bf(krl_hi[jc][rt]), a, 0, 0, 0);
-                        if (KLO)
-                            a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                                as_bf(cur_hi[s]), as_bf(krl_lo[DO_L && KLO ? jc : 0][DO_L && KLO ? rt : 0]), a, 0, 0, 0);
-                        if (YLO)
-                            a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(cur_lo[s]), as_bf(krl_hi[jc][rt]), a, 0, 0, 0);
+                        a = mma16<F16>(cur_hi[s], krl_hi[jc][rt], a);
+                        if (KLO) a = mma16<F16>(cur_hi[s], krl_lo[DO_L && KLO ? jc : 0][DO_L && KLO ? rt : 0], a);
+                        if (YLO) a = mma16<F16>(cur_lo[s], krl_hi[jc][rt], a);
                     }
+                    // fp16: unscale by the tile's and this rank column's scales before the cross-wave sum
+                    if constexpr (F16) a *= inv_s * sKs[2][F16 ? rt * 16 + c16 : 0];
                     accL[kt][rt] = a;
                 }
 #pragma unroll
@@ -404,6 +495,42 @@ __global__ __launch_bounds__(256) void k_contract_bf16(const void* __restrict__ 
         }
     };
 
+    // fp16 scaling of the Khatri-Rao columns: max_i |A^(m)(i, r)| of every factor
+    // (LDS atomics on the |x| bits), then per side 2^f_r from the product of its
+    // modes' maxima (exponents summed, so no float overflow on the way).
+    if constexpr (F16) {
+        const int N = kg.N;
+        for (int e = tid; e < N * RT; e += 256) sCm[F16 ? e / RT : 0][F16 ? e % RT : 0] = 0u;
+        __syncthreads();
+        for (int m = 0; m < N; ++m) {
+            const int tot = (int)kg.fd[m].d * R;
+            for (int e = tid; e < tot; e += 256)
+                atomicMax(&sCm[F16 ? m : 0][F16 ? e % R : 0], __float_as_uint(kg.A[m][e]) & 0x7fffffffu);
+        }
+        __syncthreads();
+        if (tid < 2 * RT) {
+            const int side = tid / RT, r = tid % RT;
+            const int m0 = side == 0 ? 0 : kg.nstar, m1 = side == 0 ? kg.nstar : N;
+            bool zero = r >= R;
+            int ex = 0;
+            float mant = 1.f;
+            for (int m = m0; m < m1 && !zero; ++m) {
+                const unsigned int b = sCm[F16 ? m : 0][F16 ? r : 0];
+                if (b == 0u || b >= 0x7f800000u) {
+                    zero = true;   // an all-zero (or non-finite) column: scale 1
+                } else {
+                    int em = 0;
+                    mant *= frexpf(__uint_as_float(b), &em);   // mantissa in [0.5, 1)
+                    ex += em;
+                }
+            }
+            const int e = zero ? 0 : clamp_exp(kF16Target - (ex + ilog2f(mant)));
+            sKs[F16 ? side : 0][F16 ? r : 0] = pow2f(e);
+            sKs[F16 ? 2 + side : 0][F16 ? r : 0] = pow2f(-e);
+        }
+        __syncthreads();
+    }
+
     // Prologue: the first steps of Y go out first, then the Khatri-Rao rows.
     constexpr int NB = kB16Depth + 1;
     Raw rbuf[NB];
@@ -432,37 +559,41 @@ __global__ __launch_bounds__(256) void k_contract_bf16(const void* __restrict__ 
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
                         const int64_t j = jw + 16 * rr + 4 * q + v;
-                        if (j < J) store_through(&PRpart[((int64_t)blockIdx.y * J + j) * ld + r], accR[rr][rt][v]);
+                        const float x = accR[rr][rt][v] * (F16 ? sKs[3][F16 ? r : 0] : 1.f);
+                        if (j < J) store_through(&PRpart[((int64_t)blockIdx.y * J + j) * ld + r], x);
                     }
                 }
             }
     }
 }
 
-// LDS of one block: static transpose / reduction tiles plus the dynamic KR_R tiles.
-static constexpr int64_t b16_static_lds(int nrt, bool do_r, bool do_l, bool ylo) {
-    return (do_r ? (int64_t)4 * (ylo ? 2 : 1) * 64 * kTrLd * 2 : 0) + (do_l ? (int64_t)2 * 4 * 2 * nrt * 64 * 16 : 0);
+// LDS of one block: static transpose / reduction tiles (and the fp16 scale
+// tables) plus the dynamic KR_R tiles.
+static constexpr int64_t b16_static_lds(int nrt, bool do_r, bool do_l, bool ylo, bool f16) {
+    return (do_r ? (int64_t)4 * (ylo ? 2 : 1) * 64 * kTrLd * 2 : 0) + (do_l ? (int64_t)2 * 4 * 2 * nrt * 64 * 16 : 0) +
+           (f16 ? (int64_t)(CPG_MAX_MODES + 4) * nrt * 16 * 4 : 0);
 }
 constexpr int64_t kB16LdsPerCu = 160 * 1024;
 
-int64_t mfma_bf16_max_cols(int rt, int roles, bool ylo, bool klo) {
+int64_t mfma_bf16_max_cols(int rt, int roles, bool ylo, bool klo, bool f16) {
     const int nrt = rt / 16;
-    const int64_t st = b16_static_lds(nrt, (roles & 1) != 0, (roles & 2) != 0, ylo);
+    const int64_t st = b16_static_lds(nrt, (roles & 1) != 0, (roles & 2) != 0, ylo, f16);
     if (!(roles & 1)) return int64_t(1) << 30;   // no KR_R tile
     const int64_t per_col = (int64_t)(klo ? 2 : 1) * rt * 2;
     const int64_t cols = (kB16LdsPerCu - st - (int64_t)(klo ? 2 : 1) * rt * 2 * 8) / per_col;
     return std::max<int64_t>(kB16Step, cols / kB16Step * kB16Step);
 }
 
-template <bool TYF, int NRT, bool DO_R, bool DO_L, bool REFINE>
+template <int YK, int NRT, bool DO_R, bool DO_L, bool REFINE, bool F16>
 static hipError_t launch_b16_one(dim3 grid, const void* Y, int64_t J, int64_t K, int64_t kcols, const MfmaBufs& o,
                                  hipStream_t s) {
-    auto kern = k_contract_bf16<TYF, NRT, DO_R, DO_L, REFINE>;
+    constexpr bool TYF = YK == 0;
+    auto kern = k_contract_bf16<YK, NRT, DO_R, DO_L, REFINE, F16>;
     const size_t dyn = DO_R ? (size_t)(REFINE ? 2 : 1) * NRT * 16 * krr_stride(kcols) * 2 : 0;
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)(kB16LdsPerCu - b16_static_lds(NRT, DO_R, DO_L, TYF && REFINE)));
+                                           (int)(kB16LdsPerCu - b16_static_lds(NRT, DO_R, DO_L, TYF && REFINE, F16)));
         if (e != hipSuccess) return e;
         attr_set = true;
     }
@@ -474,40 +605,50 @@ static hipError_t launch_b16_one(dim3 grid, const void* Y, int64_t J, int64_t K,
     return hipGetLastError();
 }
 
-template <bool TYF, int NRT, bool REFINE>
+template <int YK, int NRT, bool REFINE, bool F16>
 static hipError_t launch_b16_roles(const void* Y, int64_t J, int64_t K, const Tiling& t, int roles,
                                    const MfmaBufs& o, hipStream_t s) {
     dim3 grid((unsigned)t.n_jr, (unsigned)t.n_kc);
     const int64_t kcols = t.ktb * kB16Step;
-    if (kcols > mfma_bf16_max_cols(NRT * 16, roles, TYF && REFINE, REFINE)) return hipErrorInvalidValue;
-    if (roles == 3) return launch_b16_one<TYF, NRT, true, true, REFINE>(grid, Y, J, K, kcols, o, s);
-    if (roles == 1) return launch_b16_one<TYF, NRT, true, false, REFINE>(grid, Y, J, K, kcols, o, s);
-    if (roles == 2) return launch_b16_one<TYF, NRT, false, true, REFINE>(grid, Y, J, K, kcols, o, s);
+    if (kcols > mfma_bf16_max_cols(NRT * 16, roles, YK == 0 && REFINE, REFINE, F16)) return hipErrorInvalidValue;
+    if (roles == 3) return launch_b16_one<YK, NRT, true, true, REFINE, F16>(grid, Y, J, K, kcols, o, s);
+    if (roles == 1) return launch_b16_one<YK, NRT, true, false, REFINE, F16>(grid, Y, J, K, kcols, o, s);
+    if (roles == 2) return launch_b16_one<YK, NRT, false, true, REFINE, F16>(grid, Y, J, K, kcols, o, s);
     return hipErrorInvalidValue;
 }
 
-template <bool TYF, bool REFINE>
+template <int YK, bool REFINE, bool F16>
 static hipError_t launch_b16_nrt(const void* Y, int64_t J, int64_t K, const Tiling& t, int roles, const MfmaBufs& o,
                                  hipStream_t s) {
     switch (t.rt) {
-        case 16: return launch_b16_roles<TYF, 1, REFINE>(Y, J, K, t, roles, o, s);
-        case 32: return launch_b16_roles<TYF, 2, REFINE>(Y, J, K, t, roles, o, s);
-        case 48: return launch_b16_roles<TYF, 3, REFINE>(Y, J, K, t, roles, o, s);
-        case 64: return launch_b16_roles<TYF, 4, REFINE>(Y, J, K, t, roles, o, s);
+        case 16: return launch_b16_roles<YK, 1, REFINE, F16>(Y, J, K, t, roles, o, s);
+        case 32: return launch_b16_roles<YK, 2, REFINE, F16>(Y, J, K, t, roles, o, s);
+        case 48: return launch_b16_roles<YK, 3, REFINE, F16>(Y, J, K, t, roles, o, s);
+        case 64: return launch_b16_roles<YK, 4, REFINE, F16>(Y, J, K, t, roles, o, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+template <int YK, bool F16>
+static hipError_t launch_b16_mode(bool refine, const void* Y, int64_t J, int64_t K, const Tiling& t, int roles,
+                                  const MfmaBufs& o, hipStream_t s) {
+    return refine ? launch_b16_nrt<YK, true, F16>(Y, J, K, t, roles, o, s)
+                  : launch_b16_nrt<YK, false, F16>(Y, J, K, t, roles, o, s);
 }
 
 hipError_t launch_contract_bf16(int ydt, int mode, const void* Y, int64_t J, int64_t K, const Tiling& t, int roles,
                                 const MfmaBufs& o, hipStream_t stream) {
     if ((J % 8) != 0) return hipErrorInvalidValue;
-    const bool refine = mode == CPG_MODE_BF16_REFINED;
-    if (ydt == CPG_F32)
-        return refine ? launch_b16_nrt<true, true>(Y, J, K, t, roles, o, stream)
-                      : launch_b16_nrt<true, false>(Y, J, K, t, roles, o, stream);
-    if (ydt == CPG_BF16)
-        return refine ? launch_b16_nrt<false, true>(Y, J, K, t, roles, o, stream)
-                      : launch_b16_nrt<false, false>(Y, J, K, t, roles, o, stream);
+    const bool f16 = mode == CPG_MODE_F16_SCALED || mode == CPG_MODE_F16_SCALED_REFINED;
+    const bool refine = mode == CPG_MODE_BF16_REFINED || mode == CPG_MODE_F16_SCALED_REFINED;
+    if (f16) {
+        if (ydt == CPG_F32) return launch_b16_mode<0, true>(refine, Y, J, K, t, roles, o, stream);
+        if (ydt == CPG_BF16) return launch_b16_mode<1, true>(refine, Y, J, K, t, roles, o, stream);
+        if (ydt == CPG_F16) return launch_b16_mode<2, true>(refine, Y, J, K, t, roles, o, stream);
+        return hipErrorInvalidValue;
+    }
+    if (ydt == CPG_F32) return launch_b16_mode<0, false>(refine, Y, J, K, t, roles, o, stream);
+    if (ydt == CPG_BF16) return launch_b16_mode<1, false>(refine, Y, J, K, t, roles, o, stream);
     return hipErrorInvalidValue;
 }
 

@@ -157,3 +157,40 @@ def test_trained_network_gains_over_plain_als():
         learn.append(r1["sweeps"])
         assert r1["fit"] >= r0["fit"] - 1e-3
     assert np.mean(learn) < 0.8 * np.mean(plain)
+
+
+@pytest.mark.parametrize("sigma", [0.0, 0.5, 3.0, 40.0])
+def test_extrapolate_with_host_sigma_accepts_only_if_lower(sigma):
+    """cpals_extrapolate: the exact cost of A_new + sigma (A_new - A_prev) against
+    the oracle's explicit residual; A_new replaced exactly when that cost is
+    below the last sweep's (accept-if-lower), and the returned cost is the
+    kept model's."""
+    import paper_1204_1586_amd as P
+    _, pr, Y, A, plan = _als_problem(seed=3)
+    Yx = exact_tensor(pr["y"], "f32", pr["dims"])
+    y2 = O.norm2(Yx)
+    for _ in range(3):
+        P.cpals_step(plan, Y, A)
+    A_prev = [a.clone() for a in A]
+    c_new, _ = P.cpals_step(plan, Y, A)
+    before = exact_factors(A)
+    cost, fit, acc = P.cpals_extrapolate(plan, Y, A, A_prev, sigma)
+    D_ext = O.cost_explicit(Yx, MO.extrapolate(before, exact_factors(A_prev), sigma))
+    after = exact_factors(A)
+    print(f"  sigma {sigma}: plain {c_new:.6e} extrapolated {D_ext:.6e} accepted {acc}", flush=True)
+    if acc:
+        assert D_ext < c_new + 1e-6 * y2
+        assert abs(cost - D_ext) <= 1e-5 * y2
+        ext = MO.extrapolate(before, exact_factors(A_prev), sigma)
+        for a, b in zip(after, ext):
+            assert np.allclose(a, b, rtol=1e-6, atol=1e-6)
+    else:
+        assert D_ext > c_new - 1e-6 * y2
+        assert cost == c_new
+        for a, b in zip(after, before):
+            assert np.array_equal(a, b)
+    if sigma == 0.0:
+        # the same model: accepting it or not leaves the factors as they were
+        # (the two evaluations of its cost differ only by float32 rounding)
+        for a, b in zip(after, before):
+            assert np.array_equal(a, b)
