@@ -416,12 +416,19 @@ static int epi_rank_tile(int R) { return rank_tile(R); }
 // right side (n <= n*), K_n on the left side.
 static int64_t grad_terms(const cpgrad_plan_s* p, int n) { return n <= p->nstar ? p->Jn[n - 1] : p->Kn[n]; }
 
+// Is a side's first chain tensor (P_R or P_L) small enough for one epilogue block?
+static bool side_rows_small(const cpgrad_plan_s* p, int side, size_t elem) {
+    const int64_t rows = side == 0 ? p->J : p->K;
+    return (size_t)rows * p->ld * elem <= kEpiLargeBytes;
+}
+
 // Does the first mode of a side go through the single-block epilogue, or does
 // its chain tensor (or its Khatri-Rao block) call for the multi-block kernels?
+// (With the first gradient precomputed by the fused reduction, only the chain
+// tensor's size matters: the epilogue then forms no Khatri-Rao block for it.)
 static bool side_first_small(const cpgrad_plan_s* p, int side, size_t elem) {
     const int n = side == 0 ? p->nstar : p->nstar + 1;
-    const int64_t rows = side == 0 ? p->J : p->K;
-    return (size_t)rows * p->ld * elem <= kEpiLargeBytes && grad_terms(p, n) * p->ld <= kEpiKRCap;
+    return side_rows_small(p, side, elem) && grad_terms(p, n) * p->ld <= kEpiKRCap;
 }
 
 // Can the single-block epilogue hold every mode's gradient, factor and the
@@ -438,11 +445,13 @@ static bool epilogue_fits(const cpgrad_plan_s* p) {
 }
 
 // The fused reduction + first gradients: float32 factors on an MFMA kind, and
-// both sides walked by the single-block epilogue.
+// both sides walked by the single-block epilogue after their first gradient
+// (the reduction forms the first gradients with Khatri-Rao weights of any
+// length, generated from the factors).
 static bool fused_first_ok(const cpgrad_plan_s* p) {
     const int kind = mfma_kind(p);
-    return kind >= 2 && p->fdt == CPG_F32 && epilogue_fits(p) && side_first_small(p, 0, 4) &&
-           side_first_small(p, 1, 4);
+    return kind >= 2 && p->fdt == CPG_F32 && epilogue_fits(p) && side_rows_small(p, 0, 4) &&
+           side_rows_small(p, 1, 4);
 }
 
 template <typename TC>
@@ -478,7 +487,7 @@ static int run_side(cpgrad_plan_s* p, const FacSet<TC>& fs, int side, void* cons
     a.update = update ? 1 : 0;
     for (int n = 0; n < N; ++n) a.Gout[n] = G ? (TC*)G[n] : nullptr;
     (void)rows;
-    if (side_first_small(p, side, sizeof(TC))) {
+    if (Gpre0 ? side_rows_small(p, side, sizeof(TC)) : side_first_small(p, side, sizeof(TC))) {
         a.n_first = n_first;
         a.n_count = n_count;
         a.Z = (const TC*)Z;
