@@ -96,57 +96,106 @@ __device__ __forceinline__ void reduce_first_rows(const ReduceFirst& a, int64_t 
     const int64_t pstride = a.rows * ld;                      // floats per partial
     const int np = (int)a.nparts;
     d4s g{0.0, 0.0, 0.0, 0.0};
+    // float64 Khatri-Rao row t of modes kr_first.. (Notation 2.1 order), zero past R
+    auto weights = [&](int64_t t, double (&w)[4]) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) w[u] = 4 * q + u < R ? 1.0 : 0.0;
+        uint32_t idx = (uint32_t)t;
+        for (int m = a.kr_first; m < a.kr_first + a.kr_count; ++m) {
+            const FastDiv f = kg.fd[m];
+            const uint32_t qd = fast_div(idx, f);
+            const float* Am = kg.A[m] + (int64_t)(idx - qd * f.d) * R;
+            idx = qd;
+            float x[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) x[u] = Am[min(4 * q + u, R - 1)];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) w[u] *= (double)x[u];
+        }
+    };
+    // the reduced row (partials summed in order p = 0, 1, ...), rounded to
+    // float32, stored when Z is kept, and its weighted contribution
+    auto finish = [&](int64_t row, const d4s& acc, const double (&w)[4]) {
+        const float4 z{(float)acc.x, (float)acc.y, (float)acc.z, (float)acc.w};
+        if (a.Z) *(float4*)(a.Z + row * ld + 4 * q) = z;
+        g.x += (double)z.x * w[0];
+        g.y += (double)z.y * w[1];
+        g.z += (double)z.z * w[2];
+        g.w += (double)z.w * w[3];
+    };
+    auto add = [](d4s& acc, const float4& v) {
+        acc.x += (double)v.x;
+        acc.y += (double)v.y;
+        acc.z += (double)v.z;
+        acc.w += (double)v.w;
+    };
     if (q < nq && i < a.I) {
-        for (int64_t t = tslot; t < a.T; t += tstep) {
-            const int64_t row = rbase + t * rstride;
-            const float* src = a.parts + row * ld + 4 * q;
-            // The first batch of partials goes out before the factor loads of the
-            // weights (it does not depend on them), so both arrive in one round
-            // trip; slots past nparts re-read the last partial and are not added.
-            float4 v[kRfBatch];
+        if (np <= kRfBatch / 4) {
+            // few partials: four terms per round trip (their partial loads and
+            // weight loads all issued before any is used)
+            int64_t t = tslot;
+            for (; t + 3 * tstep < a.T; t += 4 * tstep) {
+                float4 v[kRfBatch];
 #pragma unroll
-            for (int u = 0; u < kRfBatch; ++u) v[u] = *(const float4*)(src + (int64_t)min(u, np - 1) * pstride);
-            // weights: float64 Khatri-Rao row t of modes kr_first.. (Notation 2.1 order), zero past R
-            double w[4];
+                for (int k = 0; k < 4; ++k) {
+                    const float* src = a.parts + (rbase + (t + k * tstep) * rstride) * ld + 4 * q;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) w[u] = 4 * q + u < R ? 1.0 : 0.0;
-            uint32_t idx = (uint32_t)t;
-            for (int m = a.kr_first; m < a.kr_first + a.kr_count; ++m) {
-                const FastDiv f = kg.fd[m];
-                const uint32_t qd = fast_div(idx, f);
-                const float* Am = kg.A[m] + (int64_t)(idx - qd * f.d) * R;
-                idx = qd;
-                float x[4];
+                    for (int u = 0; u < kRfBatch / 4; ++u)
+                        v[4 * k + u] = *(const float4*)(src + (int64_t)min(u, np - 1) * pstride);
+                }
+                double w[4][4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) x[u] = Am[min(4 * q + u, R - 1)];
+                for (int k = 0; k < 4; ++k) weights(t + k * tstep, w[k]);
 #pragma unroll
-                for (int u = 0; u < 4; ++u) w[u] *= (double)x[u];
+                for (int k = 0; k < 4; ++k) {
+                    d4s acc{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int u = 0; u < kRfBatch / 4; ++u)
+                        if (u < np) add(acc, v[4 * k + u]);
+                    finish(rbase + (t + k * tstep) * rstride, acc, w[k]);
+                }
             }
-            d4s acc{0.0, 0.0, 0.0, 0.0};
-            auto add = [&](const float4& v) {
-                acc.x += (double)v.x;
-                acc.y += (double)v.y;
-                acc.z += (double)v.z;
-                acc.w += (double)v.w;
-            };
+            for (; t < a.T; t += tstep) {
+                const int64_t row = rbase + t * rstride;
+                const float* src = a.parts + row * ld + 4 * q;
+                float4 v[kRfBatch / 4];
 #pragma unroll
-            for (int u = 0; u < kRfBatch; ++u)
-                if (u < np) add(v[u]);
-            // further full batches without branches, then the tail
-            int p = kRfBatch;
-            for (; p + kRfBatch <= np; p += kRfBatch) {
+                for (int u = 0; u < kRfBatch / 4; ++u) v[u] = *(const float4*)(src + (int64_t)min(u, np - 1) * pstride);
+                double w[4];
+                weights(t, w);
+                d4s acc{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int u = 0; u < kRfBatch; ++u) v[u] = *(const float4*)(src + (p + u) * pstride);
-#pragma unroll
-                for (int u = 0; u < kRfBatch; ++u) add(v[u]);
+                for (int u = 0; u < kRfBatch / 4; ++u)
+                    if (u < np) add(acc, v[u]);
+                finish(row, acc, w);
             }
-            for (; p < np; ++p) add(*(const float4*)(src + p * pstride));
-            const float4 z{(float)acc.x, (float)acc.y, (float)acc.z, (float)acc.w};
-            if (a.Z) *(float4*)(a.Z + row * ld + 4 * q) = z;
-            g.x += (double)z.x * w[0];
-            g.y += (double)z.y * w[1];
-            g.z += (double)z.z * w[2];
-            g.w += (double)z.w * w[3];
+        } else {
+            for (int64_t t = tslot; t < a.T; t += tstep) {
+                const int64_t row = rbase + t * rstride;
+                const float* src = a.parts + row * ld + 4 * q;
+                // The first batch of partials goes out before the factor loads of the
+                // weights (it does not depend on them), so both arrive in one round
+                // trip; slots past nparts re-read the last partial and are not added.
+                float4 v[kRfBatch];
+#pragma unroll
+                for (int u = 0; u < kRfBatch; ++u) v[u] = *(const float4*)(src + (int64_t)min(u, np - 1) * pstride);
+                double w[4];
+                weights(t, w);
+                d4s acc{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int u = 0; u < kRfBatch; ++u)
+                    if (u < np) add(acc, v[u]);
+                // further full batches without branches, then the tail
+                int p = kRfBatch;
+                for (; p + kRfBatch <= np; p += kRfBatch) {
+#pragma unroll
+                    for (int u = 0; u < kRfBatch; ++u) v[u] = *(const float4*)(src + (p + u) * pstride);
+#pragma unroll
+                    for (int u = 0; u < kRfBatch; ++u) add(acc, v[u]);
+                }
+                for (; p < np; ++p) add(acc, *(const float4*)(src + p * pstride));
+                finish(row, acc, w);
+            }
         }
     }
     // sum over the term slots in a fixed order: a butterfly over the slots of
