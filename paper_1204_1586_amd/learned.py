@@ -4,9 +4,12 @@ features, exact costs of extrapolated models, the network's forward pass,
 gradients and Adam updates); this module only sequences the calls and keeps
 the per-sweep bookkeeping (cost history, stopping test, statistics).
 
-Training data come from plain ALS trajectories: after sweep k from A_start to
-A, the label is the step size sigma* in SIGMA_GRID that minimises the exact
-cost of A + sigma (A - A_start) (sigma = 0 is the plain step).
+Training data come from ALS trajectories: after sweep k from A_start to A, the
+label is the step size sigma* in SIGMA_GRID that minimises the exact cost of
+A + sigma (A - A_start) (sigma = 0 is the plain step).  Half of the
+trajectories are plain ALS; the other half take the labelled extrapolation
+whenever it lowers the cost (accept-if-lower, as the learned step does at
+inference), so the network also sees the states that extrapolated runs visit.
 
 Usage (trains on seeded synthetic tensors and writes the parameters):
     python -m paper_1204_1586_amd.learned --tensors 200 --inits 10 --out weights.npz
@@ -22,8 +25,8 @@ import torch
 
 from . import _lib as L
 
-SIGMA_GRID = (0.0, 0.25, 0.5, 1.0, 2.0, 4.0, 8.0, 16.0)
-SIGMA_MAX = 16.0
+SIGMA_GRID = (0.0, 0.25, 0.5, 1.0, 2.0, 4.0, 8.0, 16.0, 32.0, 64.0)
+SIGMA_MAX = 64.0
 N_HIDDEN = 32
 
 
@@ -44,9 +47,11 @@ def new_network(params=None, seed=0):
     return m
 
 
-def collect_trajectory(plan, Y, A, sweeps, label_every=3, grid=SIGMA_GRID):
-    """Plain ALS from A (updated in place) for `sweeps` sweeps; every
-    `label_every` sweeps one (features, best sigma) pair.  Returns (X, T, fits)."""
+def collect_trajectory(plan, Y, A, sweeps, label_every=3, grid=SIGMA_GRID, follow=False):
+    """ALS from A (updated in place) for `sweeps` sweeps; every `label_every`
+    sweeps one (features, best sigma) pair.  With `follow`, the labelled
+    extrapolation is then taken (it lowers the exact cost by construction).
+    Returns (X, T, fits)."""
     feat = torch.empty(L.NFEAT, dtype=torch.float32, device="cuda")
     X, T, fits, costs = [], [], [], []
     last_sigma, last_acc = 0.0, 0
@@ -56,6 +61,7 @@ def collect_trajectory(plan, Y, A, sweeps, label_every=3, grid=SIGMA_GRID):
         costs.append(cost)
         fits.append(fit)
         L.cpals_features(plan, A, A_start, costs, k, last_sigma, last_acc, feat)
+        last_sigma, last_acc = 0.0, 0
         if k >= 2 and k % label_every == 0:
             best_s, best_c = 0.0, cost
             for s in grid[1:]:
@@ -65,6 +71,12 @@ def collect_trajectory(plan, Y, A, sweeps, label_every=3, grid=SIGMA_GRID):
             X.append(feat.cpu().numpy().copy())
             T.append(best_s)
             last_sigma, last_acc = best_s, int(best_s > 0)
+            if follow and best_s > 0:
+                # the plan's last cost is the sweep's (cp_fit_extrapolated keeps it)
+                L.cp_fit(plan, Y, A)
+                c, f, acc = L.cpals_extrapolate(plan, Y, A, A_start, best_s)
+                costs[-1], fits[-1] = c, f
+                last_acc = acc
     return (np.array(X, dtype=np.float32).reshape(-1, L.NFEAT), np.array(T, dtype=np.float32), fits)
 
 
@@ -88,9 +100,10 @@ def train(mlp, X, T, epochs=30, batch=256, lr=3e-3, seed=0, log=None):
     return hist
 
 
-def run_als(plan, Y, A, tol=1e-6, max_sweeps=5000, mlp=None):
-    """ALS from A (updated in place) until |fit_k - fit_{k-1}| < tol; with a
-    network, each sweep is a learned-extrapolation step.  Returns statistics."""
+def run_als(plan, Y, A, tol=1e-6, max_sweeps=5000, mlp=None, target_fit=None):
+    """ALS from A (updated in place) until |fit_k - fit_{k-1}| < tol (or, with
+    target_fit, until the fit reaches it); with a network, each sweep is a
+    learned-extrapolation step.  Returns statistics."""
     costs, fits = [], []
     last_sigma, last_acc, accepted, proposals = 0.0, 0, 0, 0
     torch.cuda.synchronize()
@@ -105,6 +118,8 @@ def run_als(plan, Y, A, tol=1e-6, max_sweeps=5000, mlp=None):
             last_sigma, last_acc = sg, acc
         costs.append(cost)
         fits.append(fit)
+        if target_fit is not None and fit >= target_fit:
+            break
         if len(fits) > 1 and abs(fits[-1] - fits[-2]) < tol:
             break
     wall = time.perf_counter() - t0
@@ -126,6 +141,7 @@ def main():
     ap.add_argument("--inits", type=int, default=10)
     ap.add_argument("--sweeps", type=int, default=60)
     ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--label-every", type=int, default=2)
     ap.add_argument("--out", default="learned_step.npz")
     args = ap.parse_args()
     import cpgen
@@ -140,7 +156,8 @@ def main():
         for i in range(args.inits):
             g = np.random.default_rng(np.random.SeedSequence([1204, 1586, 5, t, i]))
             A = [torch.tensor(g.standard_normal((I, pr["R"])), dtype=torch.float32).cuda() for I in pr["dims"]]
-            X, T, _ = collect_trajectory(plan, Y, A, args.sweeps)
+            X, T, _ = collect_trajectory(plan, Y, A, args.sweeps, label_every=args.label_every,
+                                         follow=(i % 2 == 1))
             Xs.append(X)
             Ts.append(T)
         print(f"tensor {t + 1}/{args.tensors} R={pr['R']} samples={sum(len(x) for x in Xs)} "
