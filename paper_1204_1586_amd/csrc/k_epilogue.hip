@@ -667,10 +667,12 @@ __device__ __forceinline__ void epilogue_body(const EpiArgs<TC>& a, double* sG, 
         if (a.update) block_gamma<TC, RT>(a, n - 1, sGam);
         if (step > 0) {
             if (a.side == 0) {
-                // vec R^(r,n) = reshape(R^(r,n+1), [J_n, I_{n+1}]) a_r^(n+1)   (eq. 3.20)
+                // next right chain tensor: the previous one contracted over its last mode
+                // with that mode's (updated) rank columns   (eq. 3.20)
                 block_ttv(cur, a.buf[buf], a.fs.A[n], a.Jn[n], a.fs.dims[n], (int64_t)1, R, a.ld, sKR, spart4);
             } else {
-                // vec L^(r,n) = reshape(L^(r,n-1), [I_{n-1}, K_{n-1}])^T a_r^(n-1)   (eq. 3.22)
+                // next left chain tensor: the previous one contracted over its first mode
+                // with that mode's (updated) rank columns   (eq. 3.22)
                 block_ttv(cur, a.buf[buf], a.fs.A[n - 2], (int64_t)1, a.fs.dims[n - 2], a.Kn[n - 1], R, a.ld, sKR,
                           spart4);
             }
@@ -685,10 +687,12 @@ __device__ __forceinline__ void epilogue_body(const EpiArgs<TC>& a, double* sG, 
             }
             __syncthreads();
         } else if (a.side == 0) {
-            // g_r^(n) = reshape(R^(r,n), [J_{n-1}, I_n])^T (a_r^(n-1) (x) ... (x) a_r^(1))   (eq. 3.12)
+            // gradient of mode n: the chain tensor's leading modes contracted with their
+            // Khatri-Rao rows   (eq. 3.12)
             block_grad<TC, RT>(cur, a.ld, a.fs, I, a.Jn[n - 1], a.Jn[n - 1], 1, 0, n - 1, sG, sKR, spart4);
         } else {
-            // g_r^(n) = reshape(L^(r,n), [I_n, K_n]) (a_r^(N) (x) ... (x) a_r^(n+1))   (eq. 3.16)
+            // gradient of mode n: the chain tensor's trailing modes contracted with their
+            // Khatri-Rao rows   (eq. 3.16)
             block_grad<TC, RT>(cur, a.ld, a.fs, I, a.Kn[n], 1, I, n, N - n, sG, sKR, spart4);
         }
         CPG_EPI_MARK(3 + 3 * step);
