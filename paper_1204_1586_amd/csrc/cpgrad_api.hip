@@ -570,27 +570,54 @@ static int all_modes_tail(cpgrad_plan_s* p, const FacSet<float>& fs, void* const
     return CPG_OK;
 }
 
+// All-mode gradient without the fused reduction: the two chains are
+// independent, so a side whose first chain tensor is large first takes its
+// first gradient and chain step on the multi-block kernels (into the side's
+// own chain buffers), then one epilogue launch walks what is left of both
+// sides, one block each.
 template <typename TC>
 static int run_both_sides(cpgrad_plan_s* p, const FacSet<TC>& fs, void* const* A, void* const* G) {
-    if (side_first_small(p, 0, sizeof(TC)) && side_first_small(p, 1, sizeof(TC))) {
-        // both chains are independent without updates: one launch, two blocks
-        EpiArgs<TC> a[2] = {epi_base<TC>(p, fs), epi_base<TC>(p, fs)};
-        for (int s = 0; s < 2; ++s) {
-            a[s].side = s;
-            a[s].n_first = s == 0 ? p->nstar : p->nstar + 1;
-            a[s].n_count = s == 0 ? p->nstar : p->N - p->nstar;
-            a[s].Z = (const TC*)(s == 0 ? p->PR : p->PL);
-            a[s].buf[0] = (TC*)p->chain[2 * s];
-            a[s].buf[1] = (TC*)p->chain[2 * s + 1];
-            for (int n = 0; n < p->N; ++n) a[s].Gout[n] = (TC*)G[n];
+    const int N = p->N, R = p->R;
+    EpiArgs<TC> a[2];
+    int na = 0;
+    for (int s = 0; s < 2; ++s) {
+        const int n = s == 0 ? p->nstar : p->nstar + 1;       // the side's first mode
+        const int n_count = s == 0 ? p->nstar : N - p->nstar;
+        const void* Z = s == 0 ? p->PR : p->PL;
+        EpiArgs<TC> e = epi_base<TC>(p, fs);
+        e.side = s;
+        for (int m = 0; m < N; ++m) e.Gout[m] = (TC*)G[m];
+        if (side_first_small(p, s, sizeof(TC))) {
+            e.n_first = n;
+            e.n_count = n_count;
+            e.Z = (const TC*)Z;
+            e.buf[0] = (TC*)p->chain[2 * s];
+            e.buf[1] = (TC*)p->chain[2 * s + 1];
+            a[na++] = e;
+            continue;
         }
-        CPG_TRY(launch_epilogue(p->fdt, p->R, a, 2, p->stream));
-        return CPG_OK;
+        if (s == 0)
+            CPG_TRY(launch_grad(p->fdt, Z, p->ld, G[n - 1], &fs, p->Jn[n - 1], p->dims[n - 1], 1, 0, n - 1, 0, 0,
+                                p->stream));
+        else
+            CPG_TRY(launch_grad(p->fdt, Z, p->ld, G[n - 1], &fs, 1, p->dims[n - 1], p->Kn[n], 0, 0, n, N - n,
+                                p->stream));
+        if (n_count == 1) continue;
+        const int nn = s == 0 ? n - 1 : n + 1;
+        if (s == 0)
+            CPG_TRY(launch_ttv(p->fdt, Z, p->chain[0], A[nn], p->Jn[nn], p->dims[nn], 1, R, p->ld, p->stream));
+        else
+            CPG_TRY(launch_ttv(p->fdt, Z, p->chain[2], A[nn - 2], 1, p->dims[nn - 2], p->Kn[nn - 1], R, p->ld,
+                               p->stream));
+        e.n_first = nn;
+        e.n_count = n_count - 1;
+        e.Z = (const TC*)p->chain[2 * s];
+        e.buf[0] = (TC*)p->chain[2 * s + 1];
+        e.buf[1] = (TC*)p->chain[2 * s];
+        a[na++] = e;
     }
-    int st = run_side<TC>(p, fs, 0, A, G, false, false, false);
-    if (st) return st;
-    // the left side reuses the chain buffers after the right side finished (stream order)
-    return run_side<TC>(p, fs, 1, A, G, false, false, false);
+    if (na) CPG_TRY(launch_epilogue(p->fdt, R, a, na, p->stream));
+    return CPG_OK;
 }
 
 // What a chain does with each gradient it forms: store it, or update that

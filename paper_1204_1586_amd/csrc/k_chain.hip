@@ -78,7 +78,90 @@ hipError_t launch_reduce_parts(int fdt, const void* parts, int64_t nparts, int64
 constexpr int kRfBatch = 16;   // partial loads in flight per thread
 constexpr int kRfThreads = 512;  // one term per thread at 64 terms x 4 float4 x 2 rows
 
-__device__ __forceinline__ void reduce_first_rows(const ReduceFirst& a, int64_t blk, const KrGen& kg, d4s* spart) {
+// Khatri-Rao weights of term t for ranks 4q..4q+3 (zero past R): the product of
+// the factor entries of modes first, first + 1, ... (Notation 2.1 order).
+// NM >= 0: that many modes, unrolled, so every factor load is issued before
+// the first product; NM < 0: `count` modes in a loop.
+// With sFac the factors come from LDS (rows of stride ld, mode after mode,
+// zero past R) by one 16-byte read per mode.
+template <int NM>
+__device__ __forceinline__ void kr_weights_rf(const KrGen& kg, int first, int count, uint32_t t, int q, int R,
+                                              int ld, const float* sFac, double (&w)[4]) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) w[u] = 4 * q + u < R ? 1.0 : 0.0;
+    uint32_t idx = t;
+    if (sFac) {
+        int64_t off = 4 * q;
+        if constexpr (NM >= 0) {
+            float4 x[NM > 0 ? NM : 1];
+#pragma unroll
+            for (int mm = 0; mm < NM; ++mm) {
+                const FastDiv f = kg.fd[first + mm];
+                const uint32_t qd = fast_div(idx, f);
+                x[mm] = *(const float4*)(sFac + off + (int64_t)(idx - qd * f.d) * ld);
+                off += (int64_t)f.d * ld;
+                idx = qd;
+            }
+#pragma unroll
+            for (int mm = 0; mm < NM; ++mm) {
+                w[0] *= (double)x[mm].x;
+                w[1] *= (double)x[mm].y;
+                w[2] *= (double)x[mm].z;
+                w[3] *= (double)x[mm].w;
+            }
+        } else {
+            for (int m = first; m < first + count; ++m) {
+                const FastDiv f = kg.fd[m];
+                const uint32_t qd = fast_div(idx, f);
+                const float4 x = *(const float4*)(sFac + off + (int64_t)(idx - qd * f.d) * ld);
+                off += (int64_t)f.d * ld;
+                idx = qd;
+                w[0] *= (double)x.x;
+                w[1] *= (double)x.y;
+                w[2] *= (double)x.z;
+                w[3] *= (double)x.w;
+            }
+        }
+        return;
+    }
+    if constexpr (NM >= 0) {
+        const float* row[NM > 0 ? NM : 1];
+#pragma unroll
+        for (int mm = 0; mm < NM; ++mm) {
+            const FastDiv f = kg.fd[first + mm];
+            const uint32_t qd = fast_div(idx, f);
+            row[mm] = kg.A[first + mm] + (int64_t)(idx - qd * f.d) * R;
+            idx = qd;
+        }
+        float x[NM > 0 ? NM : 1][4];
+#pragma unroll
+        for (int mm = 0; mm < NM; ++mm)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) x[mm][u] = row[mm][min(4 * q + u, R - 1)];
+#pragma unroll
+        for (int mm = 0; mm < NM; ++mm)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) w[u] *= (double)x[mm][u];
+    } else {
+        for (int m = first; m < first + count; ++m) {
+            const FastDiv f = kg.fd[m];
+            const uint32_t qd = fast_div(idx, f);
+            const float* Am = kg.A[m] + (int64_t)(idx - qd * f.d) * R;
+            idx = qd;
+            float x[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) x[u] = Am[min(4 * q + u, R - 1)];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) w[u] *= (double)x[u];
+        }
+    }
+}
+
+constexpr int kRfFacCap = 4096;   // floats of LDS-staged weighting factors
+
+template <int NM>
+__device__ __forceinline__ void reduce_first_rows(const ReduceFirst& a, int64_t blk, const KrGen& kg, d4s* spart,
+                                                  float* sFac) {
     const int R = kg.R;
     const int tid = threadIdx.x;
     const int ld = a.ld;
@@ -96,22 +179,33 @@ __device__ __forceinline__ void reduce_first_rows(const ReduceFirst& a, int64_t 
     const int64_t pstride = a.rows * ld;                      // floats per partial
     const int np = (int)a.nparts;
     d4s g{0.0, 0.0, 0.0, 0.0};
+    // With several terms per thread, the weighting modes' factors are first
+    // staged in LDS (when they fit), so that a term's weights cost LDS reads
+    // instead of scattered 4-byte loads; with fewer, that round trip would
+    // not pay for itself.
+    const float* fac = nullptr;
+    if (a.kr_count > 0 && a.T >= 4 * (int64_t)tstep) {
+        int64_t tot = 0;
+        for (int m = a.kr_first; m < a.kr_first + a.kr_count; ++m) tot += (int64_t)kg.fd[m].d * ld;
+        if (tot <= kRfFacCap) {
+            for (int64_t e = tid; e < tot; e += kRfThreads) {
+                int m = a.kr_first;
+                int64_t o = e;
+                while (o >= (int64_t)kg.fd[m].d * ld) {
+                    o -= (int64_t)kg.fd[m].d * ld;
+                    ++m;
+                }
+                const int64_t ii = o / ld;
+                const int r = (int)(o - ii * ld);
+                sFac[e] = r < R ? kg.A[m][ii * R + r] : 0.f;
+            }
+            __syncthreads();
+            fac = sFac;
+        }
+    }
     // float64 Khatri-Rao row t of modes kr_first.. (Notation 2.1 order), zero past R
     auto weights = [&](int64_t t, double (&w)[4]) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) w[u] = 4 * q + u < R ? 1.0 : 0.0;
-        uint32_t idx = (uint32_t)t;
-        for (int m = a.kr_first; m < a.kr_first + a.kr_count; ++m) {
-            const FastDiv f = kg.fd[m];
-            const uint32_t qd = fast_div(idx, f);
-            const float* Am = kg.A[m] + (int64_t)(idx - qd * f.d) * R;
-            idx = qd;
-            float x[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) x[u] = Am[min(4 * q + u, R - 1)];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) w[u] *= (double)x[u];
-        }
+        kr_weights_rf<NM>(kg, a.kr_first, a.kr_count, (uint32_t)t, q, R, ld, fac, w);
     };
     // the reduced row (partials summed in order p = 0, 1, ...), rounded to
     // float32, stored when Z is kept, and its weighted contribution
@@ -240,12 +334,21 @@ struct RfSides {
 
 __global__ __launch_bounds__(kRfThreads) void k_reduce_first(RfSides sd, KrGen kg, double* __restrict__ grams) {
     __shared__ d4s spart[kRfThreads];
+    __shared__ __align__(16) float sFac[kRfFacCap];
     const int64_t b = blockIdx.x;
     if (b == 0 && sd.clear_flags && threadIdx.x < 8) sd.clear_flags[threadIdx.x] = 0;
     if (b < sd.first[sd.n]) {
         int k = 0;
         while (k + 1 < sd.n && b >= sd.first[k + 1]) ++k;
-        reduce_first_rows(sd.s[k], b - sd.first[k], kg, spart);
+        const ReduceFirst& a = sd.s[k];
+        // the weights' mode count as a constant where it is small (uniform per side)
+        switch (a.kr_count) {
+            case 0: reduce_first_rows<0>(a, b - sd.first[k], kg, spart, sFac); break;
+            case 1: reduce_first_rows<1>(a, b - sd.first[k], kg, spart, sFac); break;
+            case 2: reduce_first_rows<2>(a, b - sd.first[k], kg, spart, sFac); break;
+            case 3: reduce_first_rows<3>(a, b - sd.first[k], kg, spart, sFac); break;
+            default: reduce_first_rows<-1>(a, b - sd.first[k], kg, spart, sFac); break;
+        }
     } else {
         // float64 Gram of mode m, terms in index order; the factor is staged
         // through LDS in chunks of whole rows (one round trip per chunk)
@@ -372,45 +475,131 @@ hipError_t launch_ttv(int fdt, const void* in, void* out, const void* a, int64_t
 // ---------------------------------------------------------------------------
 // gradient of one mode from a chain tensor (cp_gradient 'right' / 'left'):
 // G(i, r) = sum_{lo, hi} Z[lo + lo_n*(i + I*hi)][r] * KR_lo(lo, r) * KR_hi(hi, r)
-// one block per row i; threads split (r, term) and reduce in LDS.
+// One block per output row i.  A thread takes one four-rank column of the
+// row and every nslots-th term, with a batch of chain-tensor loads in flight
+// (the Khatri-Rao weights are formed from the factors meanwhile); its terms
+// are summed in order, then the threads of a column in a fixed order (a
+// butterfly in each wave, then the waves in order).
 // ---------------------------------------------------------------------------
+constexpr int kGradMaxThreads = 1024;
 template <typename TC>
-__global__ __launch_bounds__(256) void k_grad(const TC* __restrict__ Z, int ld, TC* __restrict__ G, FacSet<TC> fs,
-                                              int64_t lo_n, int64_t I, int64_t hi_n, int lo_first, int lo_count,
-                                              int hi_first, int hi_count) {
-    __shared__ double sred[256];
+constexpr int grad_batch() { return sizeof(TC) == 8 ? 4 : 8; }   // within 128 registers at 1024 threads
+
+template <typename TC>
+__device__ __forceinline__ void load4_d(const TC* p, double (&x)[4]);
+template <>
+__device__ __forceinline__ void load4_d<float>(const float* p, double (&x)[4]) {
+    const float4 v = *(const float4*)p;
+    x[0] = v.x;
+    x[1] = v.y;
+    x[2] = v.z;
+    x[3] = v.w;
+}
+template <>
+__device__ __forceinline__ void load4_d<double>(const double* p, double (&x)[4]) {
+    const double2 a = *(const double2*)p, b = *(const double2*)(p + 2);
+    x[0] = a.x;
+    x[1] = a.y;
+    x[2] = b.x;
+    x[3] = b.y;
+}
+
+// q = x / d, m = x - q d (32-bit division when both fit)
+__device__ __forceinline__ void divmod64(int64_t x, int64_t d, int64_t& q, int64_t& m) {
+    if (((uint64_t)x | (uint64_t)d) <= 0xffffffffull) {
+        const uint32_t q32 = (uint32_t)x / (uint32_t)d;
+        q = q32;
+    } else {
+        q = x / d;
+    }
+    m = x - q * d;
+}
+
+// w[u] *= KR(idx, r0 + u) over modes first..first+count-1 (Notation 2.1 order);
+// ranks past R read the last rank (the caller drops them)
+template <typename TC>
+__device__ __forceinline__ void kr_weights4(const FacSet<TC>& fs, int first, int count, int64_t idx, int r0,
+                                            double (&w)[4]) {
+    const int R = fs.R;
+    for (int m = 0; m < count; ++m) {
+        int64_t qd, i;
+        divmod64(idx, fs.dims[first + m], qd, i);
+        const TC* a = fs.A[first + m] + i * R;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) w[u] *= (double)a[min(r0 + u, R - 1)];
+        idx = qd;
+    }
+}
+
+template <typename TC>
+__global__ __launch_bounds__(kGradMaxThreads) void k_grad(const TC* __restrict__ Z, int ld, TC* __restrict__ G,
+                                                          FacSet<TC> fs, int64_t lo_n, int64_t I, int64_t hi_n,
+                                                          int lo_first, int lo_count, int hi_first, int hi_count) {
+    __shared__ double spart[(kGradMaxThreads / 64) * 16 * 4];
     const int R = fs.R;
     const int tid = threadIdx.x;
+    const int nq = ld >> 2;                 // four-rank columns of a row (ld <= 64)
+    int nqp = 1;
+    while (nqp < nq) nqp <<= 1;
+    const int q = tid & (nqp - 1);
+    const int nslots = (int)blockDim.x / nqp;
+    const int slot = tid / nqp;
     const int64_t i = blockIdx.x;
-    const int groups = 256 / R;
-    const int r = tid % R;
-    const int g = tid / R;
-    double acc = 0.0;
-    if (g < groups) {
-        const int64_t nterms = lo_n * hi_n;
-        for (int64_t t = g; t < nterms; t += groups) {
-            const int64_t hi = t / lo_n;
-            const int64_t lo = t - hi * lo_n;
-            const double z = (double)Z[(lo + lo_n * (i + I * hi)) * ld + r];
-            acc += z * kr_entry_d(fs, lo_first, lo_count, lo, r) * kr_entry_d(fs, hi_first, hi_count, hi, r);
+    const int64_t T = lo_n * hi_n;
+    constexpr int kGradBatch = grad_batch<TC>();
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (q < nq) {
+        for (int64_t t0 = slot; t0 < T; t0 += (int64_t)kGradBatch * nslots) {
+            double z[kGradBatch][4];
+            int64_t lo[kGradBatch], hi[kGradBatch];
+#pragma unroll
+            for (int u = 0; u < kGradBatch; ++u) {
+                const int64_t t = min(t0 + (int64_t)u * nslots, T - 1);   // the tail re-reads the last term
+                divmod64(t, lo_n, hi[u], lo[u]);
+                load4_d(Z + (lo[u] + lo_n * (i + I * hi[u])) * ld + 4 * q, z[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < kGradBatch; ++u) {
+                if (t0 + (int64_t)u * nslots < T) {
+                    double w[4] = {1.0, 1.0, 1.0, 1.0};
+                    kr_weights4(fs, lo_first, lo_count, lo[u], 4 * q, w);
+                    kr_weights4(fs, hi_first, hi_count, hi[u], 4 * q, w);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc[c] += z[u][c] * w[c];
+                }
+            }
         }
     }
-    sred[tid] = (g < groups) ? acc : 0.0;
+    for (int off = nqp; off < 64; off <<= 1)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c] += __shfl_xor(acc[c], off);
+    const int w = tid >> 6, l = tid & 63;
+    if (l < nqp)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) spart[(w * 16 + l) * 4 + c] = acc[c];
     __syncthreads();
-    if (tid < R) {
-        double v = 0.0;
-        for (int q = 0; q < groups; ++q) v += sred[q * R + tid];
-        G[i * R + tid] = (TC)v;
+    if (tid < nq) {
+        double v[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int ww = 0; ww < (int)blockDim.x / 64; ++ww)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) v[c] += spart[(ww * 16 + tid) * 4 + c];
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (4 * tid + c < R) G[i * R + 4 * tid + c] = (TC)v[c];
     }
 }
 
 hipError_t launch_grad(int fdt, const void* Z, int ld, void* G, const void* facset, int64_t lo_n, int64_t I,
                        int64_t hi_n, int lo_first, int lo_count, int hi_first, int hi_count, hipStream_t s) {
+    if ((ld & 3) != 0 || ld > 64 || I < 1) return hipErrorInvalidValue;
+    // a wide block when the row has many terms
+    const int64_t loads = lo_n * hi_n * (ld >> 2);
+    const dim3 block(loads >= 16 * kGradMaxThreads ? kGradMaxThreads : 256);
     if (fdt == CPG_F64)
-        hipLaunchKernelGGL(k_grad<double>, dim3((unsigned)I), dim3(256), 0, s, (const double*)Z, ld, (double*)G,
+        hipLaunchKernelGGL(k_grad<double>, dim3((unsigned)I), block, 0, s, (const double*)Z, ld, (double*)G,
                            *(const FacSet<double>*)facset, lo_n, I, hi_n, lo_first, lo_count, hi_first, hi_count);
     else
-        hipLaunchKernelGGL(k_grad<float>, dim3((unsigned)I), dim3(256), 0, s, (const float*)Z, ld, (float*)G,
+        hipLaunchKernelGGL(k_grad<float>, dim3((unsigned)I), block, 0, s, (const float*)Z, ld, (float*)G,
                            *(const FacSet<float>*)facset, lo_n, I, hi_n, lo_first, lo_count, hi_first, hi_count);
     return hipGetLastError();
 }

@@ -29,6 +29,7 @@
 namespace cpg {
 
 constexpr int kEpiThreads = 512;
+constexpr int kEpiChainBytes = 32768;   // LDS for the chain tensors after a side's first (two halves)
 
 __device__ __forceinline__ void wave_lds_sync() {
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
@@ -63,6 +64,13 @@ struct Raw4<double> {
         return d4{a.x * w[0], a.y * w[1], b.x * w[2], b.y * w[3]};
     }
 };
+
+// q = x / d for the small non-negative values of the index arithmetic below
+// (32-bit division when both fit)
+__device__ __forceinline__ int64_t div_small(int64_t x, int64_t d) {
+    if (((uint64_t)x | (uint64_t)d) <= 0xffffffffull) return (int64_t)((uint32_t)x / (uint32_t)d);
+    return x / d;
+}
 
 // LDS staging of n float64 entries, kStageBatch per thread in flight:
 // load(e) is called with a valid e (tails are clamped, so no load sits behind
@@ -99,7 +107,7 @@ __device__ __forceinline__ void stage_kr(const FacSet<TC>& fs, int first, int co
 #pragma unroll
         for (int u = 0; u < kStageBatch; ++u) {
             const int64_t e = min(e0 + u * kEpiThreads, n - 1);
-            idx[u] = e / ld;
+            idx[u] = div_small(e, ld);
             r[u] = (int)(e - idx[u] * ld);
             v[u] = r[u] < R ? 1.0 : 0.0;
             r[u] = r[u] < R ? r[u] : R - 1;
@@ -110,7 +118,7 @@ __device__ __forceinline__ void stage_kr(const FacSet<TC>& fs, int first, int co
             TC x[kStageBatch];
 #pragma unroll
             for (int u = 0; u < kStageBatch; ++u) {
-                const int64_t q = idx[u] / d;
+                const int64_t q = div_small(idx[u], d);
                 x[u] = A[(idx[u] - q * d) * R + r[u]];
                 idx[u] = q;
             }
@@ -127,31 +135,56 @@ __device__ __forceinline__ void stage_kr(const FacSet<TC>& fs, int first, int co
 
 constexpr int kEpiBatch = 16;   // chain-tensor loads in flight per thread
 
-// For O outputs (each four consecutive ranks) sum T weighted terms: term t of
-// output o is the four entries at addr(o, t) times the four float64 weights at
-// wt(o, t); store(o, d4) receives the sum.  Loads go out kEpiBatch at a time
-// before any is used (the chain tensors are streamed from memory by this one
-// block, so the loads in flight set its speed).  Few outputs: the terms of
-// one output are split over several threads and the parts summed in fixed
-// order.
-template <typename TC, typename Addr, typename Wt, typename Store>
-__device__ __forceinline__ void block_sum_terms(int64_t O, int64_t T, Addr addr, Wt wt, Store store, d4* spart) {
+// The terms of one output: term t is the four entries at z + t zs times the
+// four float64 weights at w + t ws.
+template <typename TC>
+struct TermRun {
+    const TC* z;
+    int64_t zs;
+    const double* w;
+    int64_t ws;
+};
+
+// For O outputs (each four consecutive ranks) sum T weighted terms; prep(o)
+// gives output o's TermRun and store(o, d4) receives the sum.  Loads go out
+// kEpiBatch at a time before any is used (the chain tensors are streamed by
+// this one block, so the loads in flight set its speed).  Few outputs: the
+// terms of one output are split over several threads and the parts summed
+// in fixed order.
+template <typename TC, typename Prep, typename Store>
+__device__ __forceinline__ void block_sum_terms(int64_t O, int64_t T, Prep prep, Store store, d4* spart) {
     const int tid = threadIdx.x;
     auto run = [&](int64_t o, int64_t t0, int64_t tstep) {
+        const TermRun<TC> tr = prep(o);
+        const TC* z = tr.z + t0 * tr.zs;
+        const double* w = tr.w + t0 * tr.ws;
+        const int64_t zs = tstep * tr.zs, ws = tstep * tr.ws;
         d4 a0{0, 0, 0, 0}, a1{0, 0, 0, 0};
         int64_t t = t0;
         // full batches without branches (so the loads stay in flight together), then the tail
         for (; t + (kEpiBatch - 1) * tstep < T; t += kEpiBatch * tstep) {
             Raw4<TC> v[kEpiBatch];
 #pragma unroll
-            for (int u = 0; u < kEpiBatch; ++u) v[u] = Raw4<TC>::load(addr(o, t + u * tstep));
+            for (int u = 0; u < kEpiBatch; ++u) v[u] = Raw4<TC>::load(z + u * zs);
 #pragma unroll
             for (int u = 0; u < kEpiBatch; u += 2) {
-                a0 = a0 + v[u].mul(wt(o, t + u * tstep));
-                a1 = a1 + v[u + 1].mul(wt(o, t + (u + 1) * tstep));
+                a0 = a0 + v[u].mul(w + u * ws);
+                a1 = a1 + v[u + 1].mul(w + (u + 1) * ws);
             }
+            z += kEpiBatch * zs;
+            w += kEpiBatch * ws;
         }
-        for (; t < T; t += tstep) a0 = a0 + Raw4<TC>::load(addr(o, t)).mul(wt(o, t));
+        if (t < T) {
+            // the tail (under kEpiBatch terms): its loads, clamped to the last
+            // term, also go out before any is used; the terms past T are not added
+            const int left = (int)div_small(T - 1 - t, tstep);   // the tail's last term: t + left * tstep
+            Raw4<TC> v[kEpiBatch];
+#pragma unroll
+            for (int u = 0; u < kEpiBatch; ++u) v[u] = Raw4<TC>::load(z + min(u, left) * zs);
+#pragma unroll
+            for (int u = 0; u < kEpiBatch; ++u)
+                if (u <= left) a0 = a0 + v[u].mul(w + u * ws);
+        }
         return a0 + a1;
     };
     if (O >= kEpiThreads) {
@@ -182,22 +215,19 @@ __device__ __forceinline__ void block_grad(const TC* __restrict__ Z, int ld, con
     const int R = fs.R;
     const int nq = ld >> 2;
     {
+        CPG_EPI_WMARK(53);
         stage_kr(fs, kr_first, kr_count, T, ld, sKR);
         __syncthreads();
+        CPG_EPI_WMARK(54);
         block_sum_terms<TC>(
             I * nq, T,
-            [&](int64_t o, int64_t t) {
-                const int64_t i = o / nq;
+            [&](int64_t o) {
+                const int64_t i = div_small(o, nq);
                 const int q4 = 4 * (int)(o - i * nq);
-                return Z + (i * si + t * st) * ld + q4;
-            },
-            [&](int64_t o, int64_t t) {
-                const int64_t i = o / nq;
-                const int q4 = 4 * (int)(o - i * nq);
-                return (const double*)(sKR + t * ld + q4);
+                return TermRun<TC>{Z + i * si * ld + q4, st * ld, (const double*)(sKR + q4), (int64_t)ld};
             },
             [&](int64_t o, d4 v) {
-                const int64_t i = o / nq;
+                const int64_t i = div_small(o, nq);
                 const int q4 = 4 * (int)(o - i * nq);
                 double* g = sG + i * RT + q4;
                 g[0] = v.x;
@@ -206,6 +236,7 @@ __device__ __forceinline__ void block_grad(const TC* __restrict__ Z, int ld, con
                 if (q4 + 3 < RT) g[3] = v.w;
             },
             spart);
+        CPG_EPI_WMARK(55);
     }
 }
 
@@ -215,31 +246,29 @@ __device__ __forceinline__ void block_ttv(const TC* __restrict__ in, TC* __restr
                                           int64_t lo_n, int64_t I, int64_t hi_n, int R, int ld, double* sA,
                                           d4* spart) {
     const int nq = ld >> 2;
+    CPG_EPI_WMARK(50);
     stage_batched(
         I * ld,
         [&](int64_t e) {
-            const int64_t i = e / ld;
+            const int64_t i = div_small(e, ld);
             const int r = (int)(e - i * ld);
             const double x = (double)a[i * R + (r < R ? r : R - 1)];
             return r < R ? x : 0.0;
         },
         [&](int64_t e, double v) { sA[e] = v; });
     __syncthreads();
+    CPG_EPI_WMARK(51);
     block_sum_terms<TC>(
         lo_n * hi_n * nq, I,
-        [&](int64_t o, int64_t i) {
-            const int64_t row = o / nq;
+        [&](int64_t o) {
+            const int64_t row = div_small(o, nq);
             const int q4 = 4 * (int)(o - row * nq);
-            const int64_t hi = row / lo_n, lo = row - (row / lo_n) * lo_n;
-            return in + (lo + lo_n * (i + I * hi)) * ld + q4;
-        },
-        [&](int64_t o, int64_t i) {
-            const int64_t row = o / nq;
-            const int q4 = 4 * (int)(o - row * nq);
-            return (const double*)(sA + i * ld + q4);
+            const int64_t hi = div_small(row, lo_n), lo = row - hi * lo_n;
+            return TermRun<TC>{in + (lo + lo_n * I * hi) * ld + q4, lo_n * ld, (const double*)(sA + q4),
+                               (int64_t)ld};
         },
         [&](int64_t o, d4 v) {
-            const int64_t row = o / nq;
+            const int64_t row = div_small(o, nq);
             const int q4 = 4 * (int)(o - row * nq);
             TC* d = out + row * ld + q4;
             d[0] = (TC)v.x;
@@ -248,6 +277,7 @@ __device__ __forceinline__ void block_ttv(const TC* __restrict__ in, TC* __restr
             d[3] = (TC)v.w;
         },
         spart);
+    CPG_EPI_WMARK(52);
 }
 
 // Gram entries of one or more staged factors: sA holds the factors back to
@@ -399,32 +429,35 @@ __device__ __forceinline__ double rcp_d(double d) {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// Rank tiles up to 16: the elimination below in the registers of single
+// Rank tiles up to 32: the elimination below in the registers of single
 // waves.  Lane l of a wave holds column l of Gamma' (lanes < R) and columns
 // i = 64 (8 q + w) + l of G^T; at step k the multipliers Gamma'_sk and the pivot
 // come from lane k by readlane, so a step needs no LDS and no barrier.  Every
 // wave with columns of G^T repeats the (small) elimination of Gamma', with
 // identical results.  *sFlag carries the outcome to the other waves.
 // I rows of G (stride RT) in sG; the solved rows are stored to A (I x R, when
-// not null) and, rounded to TC, to sF (stride RT).
-template <typename TC, int RT>
+// not null) and, rounded to TC, to sF (stride RT).  The registers hold the
+// first RE <= RT columns (R <= RE): the entries past R are zero and stay zero,
+// so a smaller RE only drops work on them.
+template <typename TC, int RT, int RE = RT>
 __device__ __forceinline__ bool wave_eliminate(int R, int64_t I, const double* sG, const double* sGam, TC* A,
                                                double* sF, int* sFlag) {
+    static_assert(RE <= RT, "register columns within the stride");
     constexpr int kSets = (kEpiGCap / RT + kEpiThreads - 1) / kEpiThreads;   // columns of G^T per lane
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
     if ((int64_t)w * 64 < I) {
-        double gc[RT], xc[kSets][RT];
+        double gc[RE], xc[kSets][RE];
 #pragma unroll
-        for (int s = 0; s < RT; ++s) gc[s] = (l < R && s < R) ? sGam[s * RT + l] : 0.0;
+        for (int s = 0; s < RE; ++s) gc[s] = (l < R && s < R) ? sGam[s * RT + l] : 0.0;
 #pragma unroll
         for (int q = 0; q < kSets; ++q) {
             const int64_t i = (int64_t)(q * (kEpiThreads / 64) + w) * 64 + l;
 #pragma unroll
-            for (int s = 0; s < RT; ++s) xc[q][s] = (i < I && s < R) ? sG[i * RT + s] : 0.0;
+            for (int s = 0; s < RE; ++s) xc[q][s] = (i < I && s < R) ? sG[i * RT + s] : 0.0;
         }
         bool ok = true;
 #pragma unroll
-        for (int k = 0; k < RT; ++k) {
+        for (int k = 0; k < RE; ++k) {
             if (k < R) {
                 // the pivot and its reciprocal estimate first, then all the
                 // step's multipliers Gamma'_sk (uniform, in scalar registers),
@@ -435,9 +468,9 @@ __device__ __forceinline__ bool wave_eliminate(int R, int64_t I, const double* s
                 ok = ok && piv > 0.0 && isfinite(piv);
                 double rp = __builtin_amdgcn_rcp(piv);
                 __builtin_amdgcn_sched_barrier(0);
-                double mk[RT];
+                double mk[RE];
 #pragma unroll
-                for (int s = 0; s < RT; ++s) mk[s] = s == k ? 0.0 : readlane_d(gc[s], k);
+                for (int s = 0; s < RE; ++s) mk[s] = s == k ? 0.0 : readlane_d(gc[s], k);
                 __builtin_amdgcn_sched_barrier(0);
                 rp = __builtin_fma(rp, __builtin_fma(-piv, rp, 1.0), rp);   // two Newton steps
                 rp = __builtin_fma(rp, __builtin_fma(-piv, rp, 1.0), rp);
@@ -447,8 +480,8 @@ __device__ __forceinline__ bool wave_eliminate(int R, int64_t I, const double* s
                 for (int q = 0; q < kSets; ++q) tx[q] = xc[q][k] * rp;
                 // row k + 1 first: the next step's pivot is ready early
 #pragma unroll
-                for (int d = 1; d < RT; ++d) {
-                    const int s = (k + d) % RT;
+                for (int d = 1; d < RE; ++d) {
+                    const int s = (k + d) % RE;
                     gc[s] -= mk[s] * tg;
 #pragma unroll
                     for (int q = 0; q < kSets; ++q) xc[q][s] -= mk[s] * tx[q];
@@ -464,7 +497,7 @@ __device__ __forceinline__ bool wave_eliminate(int R, int64_t I, const double* s
                 const int64_t i = (int64_t)(q * (kEpiThreads / 64) + w) * 64 + l;
                 if (i < I) {
 #pragma unroll
-                    for (int s = 0; s < RT; ++s) {
+                    for (int s = 0; s < RE; ++s) {
                         if (s < R) {
                             const TC v = (TC)xc[q][s];
                             if (A) A[i * R + s] = v;
@@ -480,32 +513,54 @@ __device__ __forceinline__ bool wave_eliminate(int R, int64_t I, const double* s
     return *sFlag != 0;
 }
 
-// Gram of the stored factor (rows of stride 16 in sF) on the float64 matrix
-// core, wave 0: D += F_b^T F_b over blocks F_b of four rows (rows past I read
-// as zero); lane l supplies F(i0 + l / 16, l mod 16) as both operands.
-__device__ __forceinline__ void wave_gram16(const double* sF, int64_t I, int R, double* gout) {
+// Block (ca, cb) of the Gram of the stored factor (rows of stride RT in sF) on
+// the float64 matrix core, one wave: D += F_a^T F_b over blocks of four rows
+// (rows past I read as zero), F_a = columns ca..ca+15; lane l supplies
+// F(i0 + l / 16, ca + l mod 16) as the first operand and F(i0 + l / 16,
+// cb + l mod 16) as the second.  With `mirror` the transposed block is
+// written too (the Gram is then exactly symmetric).
+template <int RT>
+__device__ __forceinline__ void wave_gram_block(const double* sF, int64_t I, int R, int ca, int cb, bool mirror,
+                                                double* gout) {
     const int l = threadIdx.x & 63;
     v4d acc = {0.0, 0.0, 0.0, 0.0};
     // four blocks per round: their LDS reads go out together, then the
     // products run in row order
     for (int64_t i0 = 0; i0 < I; i0 += 16) {
-        double v[4];
+        double va[4], vb[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int64_t i = i0 + 4 * u + (l >> 4);
-            const double x = sF[min(i, I - 1) * 16 + (l & 15)];
-            v[u] = i < I ? x : 0.0;
+            const double* row = sF + min(i, I - 1) * RT + (l & 15);
+            const double xa = row[ca], xb = row[cb];
+            va[u] = i < I ? xa : 0.0;
+            vb[u] = i < I ? xb : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v[u], v[u], acc, 0, 0, 0);
+        for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(va[u], vb[u], acc, 0, 0, 0);
     }
     // output of the float64 16x16x4 product: lane l, item j holds D[(l >> 4) + 4 j][l & 15]
-    const int c = l & 15;
+    const int c = cb + (l & 15);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const int r = (l >> 4) + 4 * j;
-        if (r < R && c < R) gout[r * R + c] = acc[j];
+        const int r = ca + (l >> 4) + 4 * j;
+        if (r < R && c < R) {
+            gout[r * R + c] = acc[j];
+            if (mirror) gout[c * R + r] = acc[j];
+        }
     }
+}
+
+// Gram of a factor with at most 16 ranks (rows of stride 16), wave 0.
+__device__ __forceinline__ void wave_gram16(const double* sF, int64_t I, int R, double* gout) {
+    wave_gram_block<16>(sF, I, R, 0, 0, false, gout);
+}
+
+// Gram of a factor with 17..32 ranks (rows of stride 32): waves 0, 1, 2 take
+// the blocks (0, 0), (0, 1) (also written transposed) and (1, 1).
+__device__ __forceinline__ void waves_gram32(const double* sF, int64_t I, int R, double* gout) {
+    const int w = threadIdx.x >> 6;
+    if (w < 3) wave_gram_block<32>(sF, I, R, w == 2 ? 16 : 0, w == 0 ? 0 : 16, w == 1, gout);
 }
 
 // eq. 2.14 for mode n (0-based): A^(n) <- G Gamma^{-1}, Gamma symmetric positive
@@ -516,7 +571,8 @@ __device__ __forceinline__ void wave_gram16(const double* sF, int64_t I, int R, 
 // positive for an SPD matrix; a pivot that is not positive and finite ends
 // the attempt (the caller retries once with `jitter`: Gamma formed again and
 // shifted by 1e-12 tr(Gamma)/R I).  Without `jitter`, sGam already holds Gamma
-// (the caller forms it while the chain step's loads are in flight).  Every thread keeps its entries of the
+// (the caller forms it while the chain step's loads are in flight).  Rank tiles up to 32
+// use the register elimination of single waves above; for a tile of 64 every thread keeps its entries of the
 // system in registers (G^T entries (s, i) with s = tid mod RT, so one
 // multiplier per step); a step needs only the pivot row and column, which
 // their owners publish to LDS (two alternating copies, one barrier per step).
@@ -552,11 +608,25 @@ __device__ __forceinline__ bool block_solve(const EpiArgs<TC>& a, int n, double*
         if (tid < R) sGam[tid * RT + tid] += 1e-12 * tr / R;
         __syncthreads();
     }
-    if constexpr (RT <= 16) {
-        if (!wave_eliminate<TC, RT>(R, I, sG, sGam, (TC*)a.fs.A[n], sPub, sFlag)) return false;
+    if constexpr (RT <= 32) {
+        // register columns: within a tile of 16 the rank rounded up to 8, 12 or 16
+        // (a choice within the tile of 32 costs the kernel register spills)
+        TC* An = (TC*)a.fs.A[n];
+        bool ok;
+        if constexpr (RT == 16) {
+            ok = R <= 8    ? wave_eliminate<TC, RT, 8>(R, I, sG, sGam, An, sPub, sFlag)
+                 : R <= 12 ? wave_eliminate<TC, RT, 12>(R, I, sG, sGam, An, sPub, sFlag)
+                           : wave_eliminate<TC, RT, 16>(R, I, sG, sGam, An, sPub, sFlag);
+        } else {
+            ok = wave_eliminate<TC, RT>(R, I, sG, sGam, An, sPub, sFlag);
+        }
+        if (!ok) return false;
         CPG_EPI_MARK(22);
         if constexpr (RT == 16) {
             if (tid < 64) wave_gram16(sPub, I, R, a.grams + (int64_t)n * R * R);
+            __syncthreads();
+        } else if constexpr (RT == 32) {
+            waves_gram32(sPub, I, R, a.grams + (int64_t)n * R * R);
             __syncthreads();
         } else {
             block_gram_rows<RT>(sPub, I, R, a.grams + (int64_t)n * R * R, spart);
@@ -645,7 +715,7 @@ __device__ __forceinline__ bool block_solve(const EpiArgs<TC>& a, int n, double*
 
 template <typename TC, int RT>
 __device__ __forceinline__ void epilogue_body(const EpiArgs<TC>& a, double* sG, double* sGam,
-                                              double* spart, double* sKR, d4* spart4, int* sFlag) {
+                                              double* spart, double* sKR, d4* spart4, int* sFlag, double* sChain) {
     const int tid = threadIdx.x;
     CPG_EPI_MARK(0);
     const int R = a.fs.R;
@@ -666,17 +736,23 @@ __device__ __forceinline__ void epilogue_body(const EpiArgs<TC>& a, double* sG, 
         // loads go out together with the chain step's
         if (a.update) block_gamma<TC, RT>(a, n - 1, sGam);
         if (step > 0) {
+            // the next chain tensor goes to one half of the LDS chain area when
+            // it fits (the halves alternate, so the one read is never the one
+            // written), else to the global chain buffer
+            const int64_t out_elems = (a.side == 0 ? a.Jn[n] : a.Kn[n - 1]) * a.ld;
+            constexpr int kHalf = kEpiChainBytes / 2 / (int)sizeof(TC);
+            TC* out = out_elems <= kHalf ? (TC*)sChain + buf * kHalf : a.buf[buf];
             if (a.side == 0) {
                 // next right chain tensor: the previous one contracted over its last mode
                 // with that mode's (updated) rank columns   (eq. 3.20)
-                block_ttv(cur, a.buf[buf], a.fs.A[n], a.Jn[n], a.fs.dims[n], (int64_t)1, R, a.ld, sKR, spart4);
+                block_ttv(cur, out, a.fs.A[n], a.Jn[n], a.fs.dims[n], (int64_t)1, R, a.ld, sKR, spart4);
             } else {
                 // next left chain tensor: the previous one contracted over its first mode
                 // with that mode's (updated) rank columns   (eq. 3.22)
-                block_ttv(cur, a.buf[buf], a.fs.A[n - 2], (int64_t)1, a.fs.dims[n - 2], a.Kn[n - 1], R, a.ld, sKR,
+                block_ttv(cur, out, a.fs.A[n - 2], (int64_t)1, a.fs.dims[n - 2], a.Kn[n - 1], R, a.ld, sKR,
                           spart4);
             }
-            cur = a.buf[buf];
+            cur = out;
             buf ^= 1;
         }
         CPG_EPI_MARK(2 + 3 * step);
@@ -755,12 +831,13 @@ __global__ __launch_bounds__(kEpiThreads) void k_epilogue(EpiArgs<TC> a0, EpiArg
     __shared__ double spart[kEpiThreads];
     __shared__ double sKR[kEpiKRCap];
     __shared__ d4 spart4[kEpiThreads];
+    __shared__ double sChain[kEpiChainBytes / 8];   // chain tensors after the first, when they fit
     __shared__ int sFlag;
     // two inlined copies so that each reads its own kernel argument directly
     if (blockIdx.x == 0)
-        epilogue_body<TC, RT>(a0, sG, sGam, spart, sKR, spart4, &sFlag);
+        epilogue_body<TC, RT>(a0, sG, sGam, spart, sKR, spart4, &sFlag, sChain);
     else
-        epilogue_body<TC, RT>(a1, sG, sGam, spart, sKR, spart4, &sFlag);
+        epilogue_body<TC, RT>(a1, sG, sGam, spart, sKR, spart4, &sFlag, sChain);
 }
 
 // ---------------------------------------------------------------------------
