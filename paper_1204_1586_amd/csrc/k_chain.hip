@@ -80,10 +80,10 @@ constexpr int kRfThreads = 512;  // one term per thread at 64 terms x 4 float4 x
 
 // Khatri-Rao weights of term t for ranks 4q..4q+3 (zero past R): the product of
 // the factor entries of modes first, first + 1, ... (Notation 2.1 order).
-// NM >= 0: that many modes, unrolled, so every factor load is issued before
-// the first product; NM < 0: `count` modes in a loop.
-// With sFac the factors come from LDS (rows of stride ld, mode after mode,
-// zero past R) by one 16-byte read per mode.
+// Without sFac the factors are read from memory, one mode at a time.  With
+// sFac they come from LDS (rows of stride ld, mode after mode, zero past R),
+// one 16-byte read per mode; NM >= 0 (= count) unrolls the modes so that all
+// the reads are issued before the first product.
 template <int NM>
 __device__ __forceinline__ void kr_weights_rf(const KrGen& kg, int first, int count, uint32_t t, int q, int R,
                                               int ld, const float* sFac, double (&w)[4]) {
@@ -113,55 +113,35 @@ __device__ __forceinline__ void kr_weights_rf(const KrGen& kg, int first, int co
             for (int m = first; m < first + count; ++m) {
                 const FastDiv f = kg.fd[m];
                 const uint32_t qd = fast_div(idx, f);
-                const float4 x = *(const float4*)(sFac + off + (int64_t)(idx - qd * f.d) * ld);
+                const float4 y = *(const float4*)(sFac + off + (int64_t)(idx - qd * f.d) * ld);
                 off += (int64_t)f.d * ld;
                 idx = qd;
-                w[0] *= (double)x.x;
-                w[1] *= (double)x.y;
-                w[2] *= (double)x.z;
-                w[3] *= (double)x.w;
+                w[0] *= (double)y.x;
+                w[1] *= (double)y.y;
+                w[2] *= (double)y.z;
+                w[3] *= (double)y.w;
             }
         }
         return;
     }
-    if constexpr (NM >= 0) {
-        const float* row[NM > 0 ? NM : 1];
+    for (int m = first; m < first + count; ++m) {
+        const FastDiv f = kg.fd[m];
+        const uint32_t qd = fast_div(idx, f);
+        const float* Am = kg.A[m] + (int64_t)(idx - qd * f.d) * R;
+        idx = qd;
+        float x[4];
 #pragma unroll
-        for (int mm = 0; mm < NM; ++mm) {
-            const FastDiv f = kg.fd[first + mm];
-            const uint32_t qd = fast_div(idx, f);
-            row[mm] = kg.A[first + mm] + (int64_t)(idx - qd * f.d) * R;
-            idx = qd;
-        }
-        float x[NM > 0 ? NM : 1][4];
+        for (int u = 0; u < 4; ++u) x[u] = Am[min(4 * q + u, R - 1)];
 #pragma unroll
-        for (int mm = 0; mm < NM; ++mm)
-#pragma unroll
-            for (int u = 0; u < 4; ++u) x[mm][u] = row[mm][min(4 * q + u, R - 1)];
-#pragma unroll
-        for (int mm = 0; mm < NM; ++mm)
-#pragma unroll
-            for (int u = 0; u < 4; ++u) w[u] *= (double)x[mm][u];
-    } else {
-        for (int m = first; m < first + count; ++m) {
-            const FastDiv f = kg.fd[m];
-            const uint32_t qd = fast_div(idx, f);
-            const float* Am = kg.A[m] + (int64_t)(idx - qd * f.d) * R;
-            idx = qd;
-            float x[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) x[u] = Am[min(4 * q + u, R - 1)];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) w[u] *= (double)x[u];
-        }
+        for (int u = 0; u < 4; ++u) w[u] *= (double)x[u];
     }
 }
 
 constexpr int kRfFacCap = 4096;   // floats of LDS-staged weighting factors
 
-template <int NM>
+template <int NM, bool STAGE>
 __device__ __forceinline__ void reduce_first_rows(const ReduceFirst& a, int64_t blk, const KrGen& kg, d4s* spart,
-                                                  float* sFac) {
+                                                  float* sFac, bool stage_fac) {
     const int R = kg.R;
     const int tid = threadIdx.x;
     const int ld = a.ld;
@@ -180,14 +160,14 @@ __device__ __forceinline__ void reduce_first_rows(const ReduceFirst& a, int64_t 
     const int np = (int)a.nparts;
     d4s g{0.0, 0.0, 0.0, 0.0};
     // With several terms per thread, the weighting modes' factors are first
-    // staged in LDS (when they fit), so that a term's weights cost LDS reads
-    // instead of scattered 4-byte loads; with fewer, that round trip would
-    // not pay for itself.
+    // staged in LDS (when they fit; the launch decides, see rf_stage_fac), so
+    // that a term's weights cost LDS reads instead of scattered 4-byte loads;
+    // with fewer, that round trip would not pay for itself.
     const float* fac = nullptr;
-    if (a.kr_count > 0 && a.T >= 4 * (int64_t)tstep) {
+    if (STAGE && stage_fac) {
         int64_t tot = 0;
         for (int m = a.kr_first; m < a.kr_first + a.kr_count; ++m) tot += (int64_t)kg.fd[m].d * ld;
-        if (tot <= kRfFacCap) {
+        {
             for (int64_t e = tid; e < tot; e += kRfThreads) {
                 int m = a.kr_first;
                 int64_t o = e;
@@ -327,27 +307,36 @@ __device__ __forceinline__ void reduce_first_rows(const ReduceFirst& a, int64_t 
 
 struct RfSides {
     ReduceFirst s[kMaxReduceSides];
+    int stage[kMaxReduceSides];           // side k stages its weighting factors in LDS (rf_stage_fac)
     int64_t first[kMaxReduceSides + 1];   // first block of each side; first[n]: blocks of all sides
     int n;
     int* clear_flags;                     // zeroed by block 0 when set
 };
 
+template <bool STAGE>
 __global__ __launch_bounds__(kRfThreads) void k_reduce_first(RfSides sd, KrGen kg, double* __restrict__ grams) {
     __shared__ d4s spart[kRfThreads];
-    __shared__ __align__(16) float sFac[kRfFacCap];
+    // kRfFacCap floats when a side stages its factors (STAGE), else none: the
+    // LDS a block holds decides whether it can start beside the blocks of the
+    // contraction still running before it
+    extern __shared__ __align__(16) float sFac[];
     const int64_t b = blockIdx.x;
     if (b == 0 && sd.clear_flags && threadIdx.x < 8) sd.clear_flags[threadIdx.x] = 0;
     if (b < sd.first[sd.n]) {
         int k = 0;
         while (k + 1 < sd.n && b >= sd.first[k + 1]) ++k;
         const ReduceFirst& a = sd.s[k];
-        // the weights' mode count as a constant where it is small (uniform per side)
-        switch (a.kr_count) {
-            case 0: reduce_first_rows<0>(a, b - sd.first[k], kg, spart, sFac); break;
-            case 1: reduce_first_rows<1>(a, b - sd.first[k], kg, spart, sFac); break;
-            case 2: reduce_first_rows<2>(a, b - sd.first[k], kg, spart, sFac); break;
-            case 3: reduce_first_rows<3>(a, b - sd.first[k], kg, spart, sFac); break;
-            default: reduce_first_rows<-1>(a, b - sd.first[k], kg, spart, sFac); break;
+        const bool st = sd.stage[k] != 0;
+        if constexpr (STAGE) {
+            // the weights' mode count as a constant where it is small (uniform per side)
+            switch (a.kr_count) {
+                case 1: reduce_first_rows<1, true>(a, b - sd.first[k], kg, spart, sFac, st); break;
+                case 2: reduce_first_rows<2, true>(a, b - sd.first[k], kg, spart, sFac, st); break;
+                case 3: reduce_first_rows<3, true>(a, b - sd.first[k], kg, spart, sFac, st); break;
+                default: reduce_first_rows<-1, true>(a, b - sd.first[k], kg, spart, sFac, st); break;
+            }
+        } else {
+            reduce_first_rows<-1, false>(a, b - sd.first[k], kg, spart, nullptr, false);
         }
     } else {
         // float64 Gram of mode m, terms in index order; the factor is staged
@@ -407,6 +396,21 @@ __global__ __launch_bounds__(kRfThreads) void k_reduce_first(RfSides sd, KrGen k
     }
 }
 
+// Does a side stage its weighting factors in LDS?  Only with several terms
+// per thread (T at least four times the term slots of a block) and factors
+// that fit kRfFacCap.
+static bool rf_stage_fac(const ReduceFirst& a, const KrGen& kg) {
+    if (a.kr_count <= 0) return false;
+    const int nq = a.ld >> 2;
+    int nqp = 1;
+    while (nqp < nq) nqp <<= 1;
+    const int tstep = kRfThreads / (nqp * rf_rows_per_block(a.side, a.ld));
+    if (a.T < 4 * (int64_t)tstep) return false;
+    int64_t tot = 0;
+    for (int m = a.kr_first; m < a.kr_first + a.kr_count; ++m) tot += (int64_t)kg.fd[m].d * a.ld;
+    return tot <= kRfFacCap;
+}
+
 hipError_t launch_reduce_first(const ReduceFirst* sides, int nsides, const KrGen& kg, double* grams,
                                hipStream_t s, int* clear_flags) {
     if (nsides < 1 || nsides > kMaxReduceSides) return hipErrorInvalidValue;
@@ -414,11 +418,14 @@ hipError_t launch_reduce_first(const ReduceFirst* sides, int nsides, const KrGen
     sd.n = nsides;
     sd.clear_flags = clear_flags;
     int64_t nb = 0;
+    bool any_stage = false;
     for (int k = 0; k < nsides; ++k) {
         const ReduceFirst& a = sides[k];
         if ((a.ld & 3) != 0 || a.ld > 64 || a.nparts < 1 || (a.out_ld != kg.R && a.out_ld != a.ld))
             return hipErrorInvalidValue;
         sd.s[k] = a;
+        sd.stage[k] = rf_stage_fac(a, kg) ? 1 : 0;
+        any_stage = any_stage || sd.stage[k];
         sd.first[k] = nb;
         const int rpb = rf_rows_per_block(a.side, a.ld);
         nb += (a.I + rpb - 1) / rpb;
@@ -426,7 +433,11 @@ hipError_t launch_reduce_first(const ReduceFirst* sides, int nsides, const KrGen
     sd.first[nsides] = nb;
     const int64_t total = nb + (grams ? kg.N : 0);
     if (total == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reduce_first, dim3((unsigned)total), dim3(kRfThreads), 0, s, sd, kg, grams);
+    if (any_stage)
+        hipLaunchKernelGGL(k_reduce_first<true>, dim3((unsigned)total), dim3(kRfThreads), kRfFacCap * sizeof(float),
+                           s, sd, kg, grams);
+    else
+        hipLaunchKernelGGL(k_reduce_first<false>, dim3((unsigned)total), dim3(kRfThreads), 0, s, sd, kg, grams);
     return hipGetLastError();
 }
 

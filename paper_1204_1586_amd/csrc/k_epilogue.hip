@@ -29,12 +29,17 @@
 namespace cpg {
 
 constexpr int kEpiThreads = 512;
-constexpr int kEpiChainBytes = 32768;   // LDS for the chain tensors after a side's first (two halves)
 
 __device__ __forceinline__ void wave_lds_sync() {
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     __builtin_amdgcn_wave_barrier();
 }
+
+// A block barrier for LDS data only: this wave's LDS operations complete, then
+// the barrier; its global stores stay in flight (a full __syncthreads waits
+// for them too).  Used where no thread reads global data another thread of
+// the block wrote since the last full barrier.
+__device__ __forceinline__ void block_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 struct d4 {
     double x, y, z, w;
@@ -134,6 +139,7 @@ __device__ __forceinline__ void stage_kr(const FacSet<TC>& fs, int first, int co
 }
 
 constexpr int kEpiBatch = 16;   // chain-tensor loads in flight per thread
+constexpr int kEpiTail = 4;     // ... in a batch's tail
 
 // The terms of one output: term t is the four entries at z + t zs times the
 // four float64 weights at w + t ws.
@@ -146,13 +152,20 @@ struct TermRun {
 };
 
 // For O outputs (each four consecutive ranks) sum T weighted terms; prep(o)
-// gives output o's TermRun and store(o, d4) receives the sum.  Loads go out
+// gives output o's TermRun and store(o, d4) receives the sum (into LDS when
+// LDS_OUT: the closing barrier then leaves global stores in flight).  Loads go out
 // kEpiBatch at a time before any is used (the chain tensors are streamed by
 // this one block, so the loads in flight set its speed).  Few outputs: the
 // terms of one output are split over several threads and the parts summed
 // in fixed order.
-template <typename TC, typename Prep, typename Store>
+template <typename TC, bool LDS_OUT, typename Prep, typename Store>
 __device__ __forceinline__ void block_sum_terms(int64_t O, int64_t T, Prep prep, Store store, d4* spart) {
+    auto close = [] {
+        if constexpr (LDS_OUT)
+            block_lds_sync();
+        else
+            __syncthreads();
+    };
     const int tid = threadIdx.x;
     auto run = [&](int64_t o, int64_t t0, int64_t tstep) {
         const TermRun<TC> tr = prep(o);
@@ -174,34 +187,52 @@ __device__ __forceinline__ void block_sum_terms(int64_t O, int64_t T, Prep prep,
             z += kEpiBatch * zs;
             w += kEpiBatch * ws;
         }
-        if (t < T) {
-            // the tail (under kEpiBatch terms): its loads, clamped to the last
-            // term, also go out before any is used; the terms past T are not added
-            const int left = (int)div_small(T - 1 - t, tstep);   // the tail's last term: t + left * tstep
-            Raw4<TC> v[kEpiBatch];
+        // the tail (under kEpiBatch terms) four terms per round trip: their
+        // loads, clamped to the last term, go out before any is used; the
+        // terms past T are not added
+        for (; t < T; t += kEpiTail * tstep) {
+            const int left = (int)div_small(T - 1 - t, tstep);   // the last term: t + left * tstep
+            Raw4<TC> v[kEpiTail];
+            double wv[kEpiTail][4];
 #pragma unroll
-            for (int u = 0; u < kEpiBatch; ++u) v[u] = Raw4<TC>::load(z + min(u, left) * zs);
+            for (int u = 0; u < kEpiTail; ++u) {
+                v[u] = Raw4<TC>::load(z + min(u, left) * zs);
+                const double* wu = w + min(u, left) * ws;
 #pragma unroll
-            for (int u = 0; u < kEpiBatch; ++u)
-                if (u <= left) a0 = a0 + v[u].mul(w + u * ws);
+                for (int c = 0; c < 4; ++c) wv[u][c] = wu[c];
+            }
+#pragma unroll
+            for (int u = 0; u < kEpiTail; ++u)
+                if (u <= left) a0 = a0 + v[u].mul(wv[u]);
+            z += kEpiTail * zs;
+            w += kEpiTail * ws;
         }
         return a0 + a1;
     };
     if (O >= kEpiThreads) {
         for (int64_t o = tid; o < O; o += kEpiThreads) store(o, run(o, 0, 1));
-        __syncthreads();
+        close();
     } else {
         const int g = kEpiThreads / (int)O;
         d4 acc{0, 0, 0, 0};
         if (tid < g * O) acc = run(tid % O, tid / (int)O, g);
         spart[tid] = acc;
-        __syncthreads();
+        block_lds_sync();
         if (tid < O) {
+            // the parts in order, eight LDS reads in flight
             d4 tot{0, 0, 0, 0};
-            for (int p = 0; p < g; ++p) tot = tot + spart[p * O + tid];
+            int p = 0;
+            for (; p + 8 <= g; p += 8) {
+                d4 u[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) u[k] = spart[(p + k) * O + tid];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) tot = tot + u[k];
+            }
+            for (; p < g; ++p) tot = tot + spart[p * O + tid];
             store(tid, tot);
         }
-        __syncthreads();
+        close();
     }
 }
 
@@ -217,9 +248,9 @@ __device__ __forceinline__ void block_grad(const TC* __restrict__ Z, int ld, con
     {
         CPG_EPI_WMARK(53);
         stage_kr(fs, kr_first, kr_count, T, ld, sKR);
-        __syncthreads();
+        block_lds_sync();
         CPG_EPI_WMARK(54);
-        block_sum_terms<TC>(
+        block_sum_terms<TC, true>(
             I * nq, T,
             [&](int64_t o) {
                 const int64_t i = div_small(o, nq);
@@ -256,9 +287,9 @@ __device__ __forceinline__ void block_ttv(const TC* __restrict__ in, TC* __restr
             return r < R ? x : 0.0;
         },
         [&](int64_t e, double v) { sA[e] = v; });
-    __syncthreads();
+    block_lds_sync();
     CPG_EPI_WMARK(51);
-    block_sum_terms<TC>(
+    block_sum_terms<TC, false>(
         lo_n * hi_n * nq, I,
         [&](int64_t o) {
             const int64_t row = div_small(o, nq);
@@ -715,7 +746,7 @@ __device__ __forceinline__ bool block_solve(const EpiArgs<TC>& a, int n, double*
 
 template <typename TC, int RT>
 __device__ __forceinline__ void epilogue_body(const EpiArgs<TC>& a, double* sG, double* sGam,
-                                              double* spart, double* sKR, d4* spart4, int* sFlag, double* sChain) {
+                                              double* spart, double* sKR, d4* spart4, int* sFlag) {
     const int tid = threadIdx.x;
     CPG_EPI_MARK(0);
     const int R = a.fs.R;
@@ -736,23 +767,15 @@ __device__ __forceinline__ void epilogue_body(const EpiArgs<TC>& a, double* sG, 
         // loads go out together with the chain step's
         if (a.update) block_gamma<TC, RT>(a, n - 1, sGam);
         if (step > 0) {
-            // the next chain tensor goes to one half of the LDS chain area when
-            // it fits (the halves alternate, so the one read is never the one
-            // written), else to the global chain buffer
-            const int64_t out_elems = (a.side == 0 ? a.Jn[n] : a.Kn[n - 1]) * a.ld;
-            constexpr int kHalf = kEpiChainBytes / 2 / (int)sizeof(TC);
-            TC* out = out_elems <= kHalf ? (TC*)sChain + buf * kHalf : a.buf[buf];
-            if (a.side == 0) {
-                // next right chain tensor: the previous one contracted over its last mode
-                // with that mode's (updated) rank columns   (eq. 3.20)
-                block_ttv(cur, out, a.fs.A[n], a.Jn[n], a.fs.dims[n], (int64_t)1, R, a.ld, sKR, spart4);
-            } else {
-                // next left chain tensor: the previous one contracted over its first mode
-                // with that mode's (updated) rank columns   (eq. 3.22)
-                block_ttv(cur, out, a.fs.A[n - 2], (int64_t)1, a.fs.dims[n - 2], a.Kn[n - 1], R, a.ld, sKR,
-                          spart4);
-            }
-            cur = out;
+            // next right chain tensor: the previous one contracted over its last mode
+            // with that mode's (updated) rank columns (eq. 3.20); next left chain
+            // tensor: contracted over its first mode (eq. 3.22)
+            const TC* fa = a.side == 0 ? a.fs.A[n] : a.fs.A[n - 2];
+            const int64_t lo_n = a.side == 0 ? a.Jn[n] : 1;
+            const int64_t tI = a.side == 0 ? a.fs.dims[n] : a.fs.dims[n - 2];
+            const int64_t hi_n = a.side == 0 ? 1 : a.Kn[n - 1];
+            block_ttv<TC>(cur, a.buf[buf], fa, lo_n, tI, hi_n, R, a.ld, sKR, spart4);
+            cur = a.buf[buf];
             buf ^= 1;
         }
         CPG_EPI_MARK(2 + 3 * step);
@@ -761,7 +784,7 @@ __device__ __forceinline__ void epilogue_body(const EpiArgs<TC>& a, double* sG, 
                 const int64_t i = o / R;
                 sG[i * RT + (o - i * R)] = (double)a.Gpre[o];
             }
-            __syncthreads();
+            block_lds_sync();
         } else if (a.side == 0) {
             // gradient of mode n: the chain tensor's leading modes contracted with their
             // Khatri-Rao rows   (eq. 3.12)
@@ -787,7 +810,12 @@ __device__ __forceinline__ void epilogue_body(const EpiArgs<TC>& a, double* sG, 
                 G[o] = (TC)sG[i * RT + (o - i * R)];
             }
         }
-        __syncthreads();
+        // an update wrote the factor and its Gram to global memory, which the
+        // next step reads; a stored gradient is not read again
+        if (a.update)
+            __syncthreads();
+        else
+            block_lds_sync();
         CPG_EPI_MARK(4 + 3 * step);
     }
 
@@ -831,13 +859,12 @@ __global__ __launch_bounds__(kEpiThreads) void k_epilogue(EpiArgs<TC> a0, EpiArg
     __shared__ double spart[kEpiThreads];
     __shared__ double sKR[kEpiKRCap];
     __shared__ d4 spart4[kEpiThreads];
-    __shared__ double sChain[kEpiChainBytes / 8];   // chain tensors after the first, when they fit
     __shared__ int sFlag;
     // two inlined copies so that each reads its own kernel argument directly
     if (blockIdx.x == 0)
-        epilogue_body<TC, RT>(a0, sG, sGam, spart, sKR, spart4, &sFlag, sChain);
+        epilogue_body<TC, RT>(a0, sG, sGam, spart, sKR, spart4, &sFlag);
     else
-        epilogue_body<TC, RT>(a1, sG, sGam, spart, sKR, spart4, &sFlag, sChain);
+        epilogue_body<TC, RT>(a1, sG, sGam, spart, sKR, spart4, &sFlag);
 }
 
 // ---------------------------------------------------------------------------
