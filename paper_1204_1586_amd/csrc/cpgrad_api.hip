@@ -86,6 +86,7 @@ int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 namespace cpg {
 int valu_max_jtb(int fdt, int rt);
+int64_t mfma_bf16_max_cols_shared(int rt, int roles, bool ylo, bool klo, bool f16, int blocks_per_cu);
 }
 
 // Tiling of one pass for the generic kernel: 64 x 64 tiles, up to `jtb`
@@ -116,13 +117,21 @@ static Tiling tile_mfma(int64_t J, int64_t K, int R, int roles, int kernel, int6
     t.n_jr = cdiv(J, 256);
     const int64_t steps = cdiv(K, 32);
     // about one block per CU: long-running blocks whose interleaved column
-    // steps sweep Y as one moving window (measured best for 64^4, rank 16)
-    const int64_t target = 256;
+    // steps sweep Y as one moving window (measured best for 64^4, rank 16).
+    // On a large tensor (32 or more steps per block at that grid) the
+    // one-sided 16-bit passes run two blocks per CU (their registers allow it)
+    // and measured fastest with four or more blocks per CU over the grid
+    // (48^5, rank 32: left pass 189 -> 127 us, right pass 235 -> 185 us; on
+    // 64^4 and 10^7 the same grids were slower).
+    const bool b16 = kernel == 3 || kernel == 4;
+    const bool b16_one = b16 && roles != 3 && cdiv(steps * t.n_jr, 256) >= 32;
+    const int64_t target = b16_one ? 1024 : 256;
     t.ktb = cols > 0 ? cdiv(cols, 32) : std::max<int64_t>(1, cdiv(steps * t.n_jr, target));
     // LDS holds the KR_R rows of a block's steps
     if (kernel == 2) t.ktb = std::min<int64_t>(t.ktb, mfma_f32_max_cols(t.rt, roles, fac_stage) / 32);
-    if (kernel == 3 || kernel == 4)
-        t.ktb = std::min<int64_t>(t.ktb, mfma_bf16_max_cols(t.rt, roles, ylo, klo, kernel == 4) / 32);
+    if (b16)
+        t.ktb = std::min<int64_t>(t.ktb, mfma_bf16_max_cols_shared(t.rt, roles, ylo, klo, kernel == 4,
+                                                                  b16_one && cols <= 0 ? 2 : 1) / 32);
     t.ktb = std::max<int64_t>(1, t.ktb);
     t.n_kc = cdiv(steps, t.ktb);
     return t;

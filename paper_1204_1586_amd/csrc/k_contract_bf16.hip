@@ -575,13 +575,19 @@ static constexpr int64_t b16_static_lds(int nrt, bool do_r, bool do_l, bool ylo,
 }
 constexpr int64_t kB16LdsPerCu = 160 * 1024;
 
-int64_t mfma_bf16_max_cols(int rt, int roles, bool ylo, bool klo, bool f16) {
+// Widest column chunk whose KR_R rows fit the LDS of a CU shared by
+// `blocks_per_cu` blocks.
+int64_t mfma_bf16_max_cols_shared(int rt, int roles, bool ylo, bool klo, bool f16, int blocks_per_cu) {
     const int nrt = rt / 16;
     const int64_t st = b16_static_lds(nrt, (roles & 1) != 0, (roles & 2) != 0, ylo, f16);
     if (!(roles & 1)) return int64_t(1) << 30;   // no KR_R tile
     const int64_t per_col = (int64_t)(klo ? 2 : 1) * rt * 2;
-    const int64_t cols = (kB16LdsPerCu - st - (int64_t)(klo ? 2 : 1) * rt * 2 * 8) / per_col;
+    const int64_t cols = (kB16LdsPerCu / blocks_per_cu - st - (int64_t)(klo ? 2 : 1) * rt * 2 * 8) / per_col;
     return std::max<int64_t>(kB16Step, cols / kB16Step * kB16Step);
+}
+
+int64_t mfma_bf16_max_cols(int rt, int roles, bool ylo, bool klo, bool f16) {
+    return mfma_bf16_max_cols_shared(rt, roles, ylo, klo, f16, 1);
 }
 
 template <int YK, int NRT, bool DO_R, bool DO_L, bool REFINE, bool F16>
