@@ -175,17 +175,18 @@ __device__ __forceinline__ void block_sum_terms(int64_t O, int64_t T, Prep prep,
         d4 a0{0, 0, 0, 0}, a1{0, 0, 0, 0};
         int64_t t = t0;
         // full batches without branches (so the loads stay in flight together), then the tail
-        for (; t + (kEpiBatch - 1) * tstep < T; t += kEpiBatch * tstep) {
-            Raw4<TC> v[kEpiBatch];
+        constexpr int kB = sizeof(TC) == 8 ? kEpiBatch / 2 : kEpiBatch;   // float64: half, within registers
+        for (; t + (kB - 1) * tstep < T; t += kB * tstep) {
+            Raw4<TC> v[kB];
 #pragma unroll
-            for (int u = 0; u < kEpiBatch; ++u) v[u] = Raw4<TC>::load(z + u * zs);
+            for (int u = 0; u < kB; ++u) v[u] = Raw4<TC>::load(z + u * zs);
 #pragma unroll
-            for (int u = 0; u < kEpiBatch; u += 2) {
+            for (int u = 0; u < kB; u += 2) {
                 a0 = a0 + v[u].mul(w + u * ws);
                 a1 = a1 + v[u + 1].mul(w + (u + 1) * ws);
             }
-            z += kEpiBatch * zs;
-            w += kEpiBatch * ws;
+            z += kB * zs;
+            w += kB * ws;
         }
         // the tail (under kEpiBatch terms) four terms per round trip: their
         // loads, clamped to the last term, go out before any is used; the
