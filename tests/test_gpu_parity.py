@@ -51,6 +51,8 @@ CASES = [
     ((4, 3, 5, 4, 3, 2, 6), 10, "f32"),       # 7-D, J_{n*} = 60
     ((10, 1, 12, 1, 8), 6, "f32"),            # unit modes
     ((4, 65, 300), 5, "f32"),                 # J = 260: a 256-row block plus a ragged 4-row one
+    ((8, 8, 44, 44, 44), 8, "f32"),           # P_L above 2 MB: first gradient and chain step on the
+    ((8, 8, 44, 44, 44), 4, "f64"),           # multi-block kernels, both sides' rest in one epilogue launch
 ]
 
 
@@ -226,7 +228,9 @@ def _als_bounds(Yx, A_start, A_end, form, sweeps=1):
                                             ((20, 30, 40, 50), 16, "f32"), ((36, 20, 28, 33), 24, "f32"),
                                             ((5, 6, 3, 4, 2, 3, 5), 10, "f32"), ((6, 5, 4, 6, 5, 4, 6), 10, "f32"),
                                             ((64, 64, 64, 64), 16, "f32"), ((8, 9, 10), 3, "f32"),
-                                            ((12, 10, 14, 9), 7, "f32")])
+                                            ((12, 10, 14, 9), 7, "f32"), ((34, 36, 40), 32, "f32"),
+                                            ((15, 17, 19), 17, "f64"), ((8, 8, 44, 44, 44), 8, "f32"),
+                                            ((8, 8, 44, 44, 44), 4, "f64")])
 def test_als_sweep_matches_oracle(dims, R, storage):
     print(f"[als] dims={dims} R={R} storage={storage}", flush=True)
     P, pr, Y, A, plan = _als_setup(dims, R, storage)
