@@ -620,15 +620,39 @@ hipError_t launch_grad(int fdt, const void* Z, int ld, void* G, const void* facs
 // ---------------------------------------------------------------------------
 template <typename TC>
 __global__ __launch_bounds__(256) void k_grams(FacSet<TC> fs, double* __restrict__ grams) {
+    // the factor is staged through LDS in chunks of whole rows (coalesced, one
+    // round trip per chunk); each entry still sums its rows in index order
+    constexpr int kChunk = 4096;
+    __shared__ double sA[kChunk];
     const int n = blockIdx.x;
     const int R = fs.R;
     const TC* A = fs.A[n];
     const int64_t I = fs.dims[n];
-    for (int e = threadIdx.x; e < R * R; e += 256) {
-        const int r = e / R, c = e - (e / R) * R;
-        double acc = 0.0;
-        for (int64_t i = 0; i < I; ++i) acc += (double)A[i * R + r] * (double)A[i * R + c];
-        grams[(int64_t)n * R * R + e] = acc;
+    const int64_t rows_per = kChunk / R;
+    constexpr int kE = 4;   // Gram entries per thread (R <= 64: R * R <= 4096 = 256 x 16, in passes)
+    for (int e0 = 0; e0 < R * R; e0 += 256 * kE) {
+        double acc[kE] = {0.0, 0.0, 0.0, 0.0};
+        for (int64_t i0 = 0; i0 < I; i0 += rows_per) {
+            const int64_t nf = min(rows_per, I - i0) * R;
+            __syncthreads();   // the previous chunk is consumed
+#pragma unroll 8
+            for (int64_t e = threadIdx.x; e < nf; e += 256) sA[e] = (double)A[i0 * R + e];
+            __syncthreads();
+            const int64_t nr = nf / R;
+#pragma unroll
+            for (int k = 0; k < kE; ++k) {
+                const int e = e0 + threadIdx.x + 256 * k;
+                if (e < R * R) {
+                    const int r = e / R, c = e - (e / R) * R;
+                    for (int64_t i = 0; i < nr; ++i) acc[k] += sA[i * R + r] * sA[i * R + c];
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kE; ++k) {
+            const int e = e0 + threadIdx.x + 256 * k;
+            if (e < R * R) grams[(int64_t)n * R * R + e] = acc[k];
+        }
     }
 }
 

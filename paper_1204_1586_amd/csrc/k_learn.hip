@@ -69,30 +69,48 @@ struct FeatArgs {
 template <typename TC>
 __global__ __launch_bounds__(kLearnThreads) void k_features(FacSet<TC> A, FacSet<TC> As, FacSet<TC> Dp, FeatArgs fa,
                                                             float* __restrict__ feat) {
-    __shared__ double sbuf[kLearnThreads];
+    constexpr int kWaves = kLearnThreads / 64;
+    __shared__ double sw[CPG_MAX_MODES][4][kWaves];   // per-wave sums
     __shared__ double st[CPG_MAX_MODES][4];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, w = tid >> 6;
     const int N = A.N, R = A.R;
+    // per mode: each thread's terms in order, a butterfly in each wave, the
+    // wave sums to LDS (no block barrier between modes); Dp <- A - As on the
+    // way (each entry is read, then overwritten, by the same thread)
     for (int n = 0; n < N; ++n) {
         const int64_t m = A.dims[n] * R;
+        TC* dp = (TC*)Dp.A[n];
         double uu = 0, aa = 0, ud = 0, dd = 0;
         for (int64_t e = tid; e < m; e += kLearnThreads) {
             const double a = (double)A.A[n][e];
             const double u = a - (double)As.A[n][e];
-            const double d = fa.have_prev ? (double)Dp.A[n][e] : 0.0;
+            const double d = fa.have_prev ? (double)dp[e] : 0.0;
+            dp[e] = (TC)u;
             uu += u * u;
             aa += a * a;
             ud += u * d;
             dd += d * d;
         }
-        const double s0 = block_sum(uu, sbuf), s1 = block_sum(aa, sbuf), s2 = block_sum(ud, sbuf),
-                     s3 = block_sum(dd, sbuf);
-        if (tid == 0) {
-            st[n][0] = s0;
-            st[n][1] = s1;
-            st[n][2] = s2;
-            st[n][3] = s3;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            uu += __shfl_xor(uu, o);
+            aa += __shfl_xor(aa, o);
+            ud += __shfl_xor(ud, o);
+            dd += __shfl_xor(dd, o);
         }
+        if ((tid & 63) == 0) {
+            sw[n][0][w] = uu;
+            sw[n][1][w] = aa;
+            sw[n][2][w] = ud;
+            sw[n][3][w] = dd;
+        }
+    }
+    __syncthreads();
+    if (tid < 4 * N) {   // the waves in order
+        const int n = tid >> 2, k = tid & 3;
+        double v = 0.0;
+        for (int ww = 0; ww < kWaves; ++ww) v += sw[n][k][ww];
+        st[n][k] = v;
     }
     __syncthreads();
     if (tid == 0) {
@@ -130,12 +148,6 @@ __global__ __launch_bounds__(kLearnThreads) void k_features(FacSet<TC> A, FacSet
         f[10] = (float)(log1p((double)fa.last_sigma) / log1p(32.0));
         f[11] = (float)fa.last_accept;
         for (int k = 0; k < 12; ++k) feat[k] = f[k];
-    }
-    // Dp <- A - As
-    for (int n = 0; n < N; ++n) {
-        const int64_t m = A.dims[n] * R;
-        TC* d = (TC*)Dp.A[n];
-        for (int64_t e = tid; e < m; e += kLearnThreads) d[e] = (TC)((double)A.A[n][e] - (double)As.A[n][e]);
     }
 }
 

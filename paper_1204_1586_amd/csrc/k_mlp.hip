@@ -52,18 +52,45 @@ __device__ __forceinline__ float mlp_forward_one(const float* P, const MlpDims& 
     return d.smax * sigmoidf_(z);
 }
 
+// Inference: eight samples per 256-thread block, one lane per hidden unit, so
+// a layer costs one pass over its inputs instead of one per unit (each unit's
+// sums run in the order of mlp_forward_one, so the results are the same).
+constexpr int kFwdSamples = 256 / kMlpMaxHidden;
 __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ params, MlpDims d,
                                                      const float* __restrict__ X, int batch,
                                                      float* __restrict__ sigma) {
     extern __shared__ float sP[];
-    const int64_t np = mlp_nparams(d.F, d.H);
+    __shared__ float sX[kFwdSamples][kMlpMaxIn], sH1[kFwdSamples][kMlpMaxHidden], sH2[kFwdSamples][kMlpMaxHidden];
+    const int F = d.F, H = d.H;
+    const int64_t np = mlp_nparams(F, H);
     for (int64_t e = threadIdx.x; e < np; e += blockDim.x) sP[e] = params[e];
+    const int sl = threadIdx.x / kMlpMaxHidden, i = threadIdx.x % kMlpMaxHidden;
+    const int s = blockIdx.x * kFwdSamples + sl;
+    if (s < batch && i < F) sX[sl][i] = X[(int64_t)s * F + i];
     __syncthreads();
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= batch) return;
-    float x[kMlpMaxIn], h1[kMlpMaxHidden], h2[kMlpMaxHidden], z;
-    for (int f = 0; f < d.F; ++f) x[f] = X[(int64_t)s * d.F + f];
-    sigma[s] = mlp_forward_one(sP, d, x, h1, h2, &z);
+    const float* W1 = sP;
+    const float* b1 = W1 + H * F;
+    const float* W2 = b1 + H;
+    const float* b2 = W2 + H * H;
+    const float* w3 = b2 + H;
+    const bool on = s < batch && i < H;
+    if (on) {
+        float a = b1[i];
+        for (int f = 0; f < F; ++f) a += W1[i * F + f] * sX[sl][f];
+        sH1[sl][i] = tanhf(a);
+    }
+    __syncthreads();
+    if (on) {
+        float a = b2[i];
+        for (int j = 0; j < H; ++j) a += W2[i * H + j] * sH1[sl][j];
+        sH2[sl][i] = tanhf(a);
+    }
+    __syncthreads();
+    if (s < batch && i == 0) {
+        float z = w3[H];
+        for (int k = 0; k < H; ++k) z += w3[k] * sH2[sl][k];
+        sigma[s] = d.smax * sigmoidf_(z);
+    }
 }
 
 // Per-block partial gradient over up to kMlpSamples samples.
@@ -290,8 +317,8 @@ int cpmlp_get_params(cpmlp_t q, float* host, int64_t n) {
 
 int cpmlp_forward(cpmlp_t q, const float* X, int batch, float* sigma) {
     if (!q || !X || !sigma || batch < 1) return CPG_ERR_INVALID;
-    hipLaunchKernelGGL(k_mlp_forward, dim3((batch + 255) / 256), dim3(256), q->np * sizeof(float), q->stream,
-                       q->params, q->d, X, batch, sigma);
+    hipLaunchKernelGGL(k_mlp_forward, dim3((batch + kFwdSamples - 1) / kFwdSamples), dim3(256),
+                       q->np * sizeof(float), q->stream, q->params, q->d, X, batch, sigma);
     return hipGetLastError() == hipSuccess ? CPG_OK : CPG_ERR_HIP;
 }
 
@@ -324,8 +351,8 @@ int cpmlp_destroy(cpmlp_t q) {
 
 namespace cpg {
 hipError_t launch_mlp_forward(cpmlp_t q, const float* X, int batch, float* sigma, hipStream_t s) {
-    hipLaunchKernelGGL(k_mlp_forward, dim3((batch + 255) / 256), dim3(256), q->np * sizeof(float), s, q->params,
-                       q->d, X, batch, sigma);
+    hipLaunchKernelGGL(k_mlp_forward, dim3((batch + kFwdSamples - 1) / kFwdSamples), dim3(256),
+                       q->np * sizeof(float), s, q->params, q->d, X, batch, sigma);
     return hipGetLastError();
 }
 int mlp_num_inputs(cpmlp_t q) { return q->d.F; }
