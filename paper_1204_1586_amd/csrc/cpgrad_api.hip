@@ -244,9 +244,9 @@ static int configure(cpgrad_plan_s* p) {
     for (int n = 0; n < N; ++n) p->fd[n] = make_fastdiv((uint32_t)p->dims[n]);
     const size_t oG = off;      off += al(maxI * R * a);
     const size_t oGr = off;     off += al((size_t)N * p->R * p->R * 8);
-    const size_t oS = off;      off += al(16 * 8);
+    // scal (16 doubles) and flags (16 ints) back to back: one copy reads both back
+    const size_t oS = off;      off += al(16 * 8 + 16 * sizeof(int));
     const size_t oRed = off;    off += al(kRedScratch * 8);
-    const size_t oF = off;      off += al(16 * sizeof(int));
     const size_t oRp = off;     off += al(2 * kEpiRowsMaxBlocks * 8);
     if (off > p->ws_bytes) {
         if (p->ws_external) return CPG_ERR_SCRATCH;
@@ -272,7 +272,7 @@ static int configure(cpgrad_plan_s* p) {
     p->grams = (double*)(b + oGr);
     p->scal = (double*)(b + oS);
     p->red = (double*)(b + oRed);
-    p->flags = (int*)(b + oF);
+    p->flags = (int*)(b + oS + 16 * 8);
     p->rpart = (double*)(b + oRp);
 
     p->bound = nullptr;
@@ -681,13 +681,13 @@ static int left_chain(cpgrad_plan_s* p, const AnyFacSet& fs, void* const* A, voi
 }
 
 static int readback(cpgrad_plan_s* p, double* cost_out, double* fit_out) {
-    if (hipMemcpyAsync(p->host, p->scal, 8 * sizeof(double), hipMemcpyDeviceToHost, p->stream) != hipSuccess)
-        return CPG_ERR_HIP;
-    if (hipMemcpyAsync(p->host + 8, p->flags, sizeof(int), hipMemcpyDeviceToHost, p->stream) != hipSuccess)
+    // scal[0..15] and flags[0] in one copy (they are contiguous on the device)
+    if (hipMemcpyAsync(p->host, p->scal, 16 * sizeof(double) + sizeof(int), hipMemcpyDeviceToHost, p->stream) !=
+        hipSuccess)
         return CPG_ERR_HIP;
     if (hipStreamSynchronize(p->stream) != hipSuccess) return CPG_ERR_HIP;
     int fl = 0;
-    std::memcpy(&fl, p->host + 8, sizeof(int));
+    std::memcpy(&fl, p->host + 16, sizeof(int));
     if (cost_out) *cost_out = p->host[2];
     if (fit_out) *fit_out = p->host[3];
     if (fl & 1) return CPG_ERR_NOT_SPD;
@@ -868,8 +868,9 @@ static int ensure_learn(cpgrad_plan_s* p) {
     p->l_dprev = p->lws + fb;
     p->l_ext = p->lws + 2 * fb;
     p->l_feat = (float*)(p->lws + 3 * fb);
-    p->l_sigma = p->l_feat + 32;
-    p->l_accept = (int*)(p->l_sigma + 4);
+    // sigma and the accept flag sit in scal[12], scal[13], so the readback copy carries them
+    p->l_sigma = (float*)(p->scal + 12);
+    p->l_accept = (int*)(p->scal + 13);
     p->have_prev = 0;
     return hipMemsetAsync(p->lws, 0, bytes, p->stream) == hipSuccess ? CPG_OK : CPG_ERR_HIP;
 }
@@ -1090,7 +1091,7 @@ int cpgrad_plan(cpgrad_plan_t* out, int N, const int64_t* dims, int R, int y_dty
         return st;
     }
     void* h = nullptr;
-    if (hipHostMalloc(&h, 16 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc(&h, 32 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
         delete p;
         return CPG_ERR_NOMEM;
     }
@@ -1347,11 +1348,9 @@ int cpals_extrapolate(cpgrad_plan_t p, const void* Y, void* const* A_new, const 
     st = fit_core(p, Y, e, 8);      // exact cost of the extrapolated factors in scal[8]
     if (st) return st;
     CPG_TRY(launch_accept(p->fdt, a.ptr(p->fdt), e.ptr(p->fdt), p->scal, p->l_accept, p->stream));
-    if (hipMemcpyAsync(p->host + 11, p->l_accept, sizeof(int), hipMemcpyDeviceToHost, p->stream) != hipSuccess)
-        return CPG_ERR_HIP;
-    st = readback(p, cost_out, fit_out);   // waits for the stream
+    st = readback(p, cost_out, fit_out);   // waits for the stream; carries the accept flag
     int acc = 0;
-    std::memcpy(&acc, p->host + 11, sizeof(int));
+    std::memcpy(&acc, p->host + 13, sizeof(int));
     if (accepted) *accepted = acc;
     return st;
 }
@@ -1378,14 +1377,11 @@ int cpals_learned_step(cpgrad_plan_t p, cpmlp_t m, const void* Y, void* const* A
     st = fit_core(p, Y, e, 8);      // exact cost of the extrapolated factors in scal[8]
     if (st) return st;
     CPG_TRY(launch_accept(p->fdt, a.ptr(p->fdt), e.ptr(p->fdt), p->scal, p->l_accept, p->stream));
-    if (hipMemcpyAsync(p->host + 10, p->l_sigma, sizeof(float), hipMemcpyDeviceToHost, p->stream) != hipSuccess ||
-        hipMemcpyAsync(p->host + 11, p->l_accept, sizeof(int), hipMemcpyDeviceToHost, p->stream) != hipSuccess)
-        return CPG_ERR_HIP;
     st = readback(p, cost_out, fit_out);   // waits for the stream
     float sg = 0.f;
     int acc = 0;
-    std::memcpy(&sg, p->host + 10, sizeof(float));
-    std::memcpy(&acc, p->host + 11, sizeof(int));
+    std::memcpy(&sg, p->host + 12, sizeof(float));
+    std::memcpy(&acc, p->host + 13, sizeof(int));
     if (accepted) *accepted = acc;
     if (sigma_out) *sigma_out = sg;
     return st;
