@@ -612,7 +612,7 @@ __device__ __forceinline__ void waves_gram32(const double* sF, int64_t I, int R,
 // formed.  G in sG is only read, so a retry and the cost can use it again.
 // Returns false, leaving A^(n) and grams[n] untouched, if Gamma is not
 // positive definite.
-template <typename TC, int RT>
+template <typename TC, int RT, int RE = RT>
 __device__ __forceinline__ bool block_solve(const EpiArgs<TC>& a, int n, double* sG, double* sGam, double* sPub,
                                             double* spart, int* sFlag, bool jitter) {
     static_assert(kEpiThreads % RT == 0, "a thread's entries of G^T share one row of the system");
@@ -641,8 +641,9 @@ __device__ __forceinline__ bool block_solve(const EpiArgs<TC>& a, int n, double*
         __syncthreads();
     }
     if constexpr (RT <= 32) {
-        // register columns: within a tile of 16 the rank rounded up to 8, 12 or 16
-        // (a choice within the tile of 32 costs the kernel register spills)
+        // register columns: within a tile of 16 the rank rounded up to 8, 12 or 16;
+        // within the tile of 32 a kernel instance of its own per choice (RE: 20 or
+        // 32), since a run-time choice there costs the kernel register spills
         TC* An = (TC*)a.fs.A[n];
         bool ok;
         if constexpr (RT == 16) {
@@ -650,7 +651,7 @@ __device__ __forceinline__ bool block_solve(const EpiArgs<TC>& a, int n, double*
                  : R <= 12 ? wave_eliminate<TC, RT, 12>(R, I, sG, sGam, An, sPub, sFlag)
                            : wave_eliminate<TC, RT, 16>(R, I, sG, sGam, An, sPub, sFlag);
         } else {
-            ok = wave_eliminate<TC, RT>(R, I, sG, sGam, An, sPub, sFlag);
+            ok = wave_eliminate<TC, RT, RE>(R, I, sG, sGam, An, sPub, sFlag);
         }
         if (!ok) return false;
         CPG_EPI_MARK(22);
@@ -745,7 +746,7 @@ __device__ __forceinline__ bool block_solve(const EpiArgs<TC>& a, int n, double*
     return true;
 }
 
-template <typename TC, int RT>
+template <typename TC, int RT, int RE>
 __device__ __forceinline__ void epilogue_body(const EpiArgs<TC>& a, double* sG, double* sGam,
                                               double* spart, double* sKR, d4* spart4, int* sFlag) {
     const int tid = threadIdx.x;
@@ -801,7 +802,7 @@ __device__ __forceinline__ void epilogue_body(const EpiArgs<TC>& a, double* sG, 
             bool solved = false;
             for (int attempt = 0; attempt < 2 && !solved; ++attempt) {
                 if (attempt > 0) __syncthreads();
-                solved = block_solve<TC, RT>(a, n - 1, sG, sGam, sKR, spart, sFlag, attempt == 1);
+                solved = block_solve<TC, RT, RE>(a, n - 1, sG, sGam, sKR, spart, sFlag, attempt == 1);
             }
             if (!solved && tid == 0) atomicOr(a.flags, 1);
         } else if (!(step == 0 && a.Gpre == a.Gout[n - 1])) {
@@ -853,7 +854,7 @@ __device__ __forceinline__ void epilogue_body(const EpiArgs<TC>& a, double* sG, 
     }
 }
 
-template <typename TC, int RT>
+template <typename TC, int RT, int RE = RT>
 __global__ __launch_bounds__(kEpiThreads) void k_epilogue(EpiArgs<TC> a0, EpiArgs<TC> a1) {
     __shared__ double sG[kEpiGCap];
     __shared__ double sGam[RT * RT];
@@ -863,9 +864,9 @@ __global__ __launch_bounds__(kEpiThreads) void k_epilogue(EpiArgs<TC> a0, EpiArg
     __shared__ int sFlag;
     // two inlined copies so that each reads its own kernel argument directly
     if (blockIdx.x == 0)
-        epilogue_body<TC, RT>(a0, sG, sGam, spart, sKR, spart4, &sFlag);
+        epilogue_body<TC, RT, RE>(a0, sG, sGam, spart, sKR, spart4, &sFlag);
     else
-        epilogue_body<TC, RT>(a1, sG, sGam, spart, sKR, spart4, &sFlag);
+        epilogue_body<TC, RT, RE>(a1, sG, sGam, spart, sKR, spart4, &sFlag);
 }
 
 // ---------------------------------------------------------------------------
@@ -1162,8 +1163,10 @@ static hipError_t epi_dispatch(int R, const EpiArgs<TC>* args, int nsides, hipSt
         hipLaunchKernelGGL((k_epilogue<TC, 4>), dim3(nsides), dim3(kEpiThreads), 0, s, a0, a1);
     else if (R <= 16)
         hipLaunchKernelGGL((k_epilogue<TC, 16>), dim3(nsides), dim3(kEpiThreads), 0, s, a0, a1);
+    else if (R <= 20)
+        hipLaunchKernelGGL((k_epilogue<TC, 32, 20>), dim3(nsides), dim3(kEpiThreads), 0, s, a0, a1);
     else if (R <= 32)
-        hipLaunchKernelGGL((k_epilogue<TC, 32>), dim3(nsides), dim3(kEpiThreads), 0, s, a0, a1);
+        hipLaunchKernelGGL((k_epilogue<TC, 32, 32>), dim3(nsides), dim3(kEpiThreads), 0, s, a0, a1);
     else
         hipLaunchKernelGGL((k_epilogue<TC, 64>), dim3(nsides), dim3(kEpiThreads), 0, s, a0, a1);
     return hipGetLastError();
