@@ -811,15 +811,48 @@ __device__ __forceinline__ double yval<_Float16>(const _Float16* p, int64_t e) {
     return (double)(float)p[e];
 }
 
+// Y is read in 16-byte chunks (Y is 16-byte aligned), four chunks in flight
+// per thread; the entries past the last whole chunk go to block 0.  Each
+// thread sums its chunks in order, the block in a fixed tree, the blocks in
+// the second stage: the result does not depend on timing.
 template <typename TY>
 __global__ __launch_bounds__(256) void k_norm2_stage1(const TY* __restrict__ Y, int64_t n,
                                                       double* __restrict__ scratch) {
     __shared__ double sbuf[256];
+    constexpr int kPer = 16 / (int)sizeof(TY);   // entries per chunk
+    constexpr int kIn = 4;                      // chunks in flight
+    const int64_t nch = n / kPer;
+    const int64_t stride = (int64_t)gridDim.x * 256;
     double acc = 0.0;
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
-        const double v = yval(Y, e);
-        acc += v * v;
+    int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    for (; c + (kIn - 1) * stride < nch; c += kIn * stride) {
+        uint4 v[kIn];
+#pragma unroll
+        for (int u = 0; u < kIn; ++u) v[u] = *(const uint4*)(Y + (c + u * stride) * kPer);
+#pragma unroll
+        for (int u = 0; u < kIn; ++u) {
+            const TY* x = reinterpret_cast<const TY*>(&v[u]);
+#pragma unroll
+            for (int k = 0; k < kPer; ++k) {
+                const double d = yval(x, k);
+                acc += d * d;
+            }
+        }
     }
+    for (; c < nch; c += stride) {
+        const uint4 v = *(const uint4*)(Y + c * kPer);
+        const TY* x = reinterpret_cast<const TY*>(&v);
+#pragma unroll
+        for (int k = 0; k < kPer; ++k) {
+            const double d = yval(x, k);
+            acc += d * d;
+        }
+    }
+    if (blockIdx.x == 0)
+        for (int64_t e = nch * kPer + threadIdx.x; e < n; e += 256) {
+            const double d = yval(Y, e);
+            acc += d * d;
+        }
     const double t = block_sum_256(acc, sbuf);
     if (threadIdx.x == 0) scratch[blockIdx.x] = t;
 }
