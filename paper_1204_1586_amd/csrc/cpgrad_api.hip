@@ -36,6 +36,7 @@ struct cpgrad_plan_s {
     void* PR = nullptr;
     void* PL = nullptr;
     void* chain[4] = {nullptr, nullptr, nullptr, nullptr};
+    size_t prpart_bytes = 0, plpart_bytes = 0;   // sizes of the split-partial buffers
     void* PRpart = nullptr;
     void* PLpart = nullptr;
     FastDiv fd[CPG_MAX_MODES];  // mode sizes as multiply-shift divisors (kernels unravel row indices)
@@ -87,6 +88,9 @@ int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 namespace cpg {
 int valu_max_jtb(int fdt, int rt);
 int64_t mfma_bf16_max_cols_shared(int rt, int roles, bool ylo, bool klo, bool f16, int blocks_per_cu);
+hipError_t launch_grad_split(int fdt, const void* Z, int ld, void* G, const void* facset, int64_t lo_n, int64_t I,
+                             int64_t hi_n, int lo_first, int lo_count, int hi_first, int hi_count, void* scratch,
+                             size_t scratch_bytes, hipStream_t s);
 }
 
 // Tiling of one pass for the generic kernel: 64 x 64 tiles, up to `jtb`
@@ -268,6 +272,8 @@ static int configure(cpgrad_plan_s* p) {
     p->chain[3] = b + oC3;
     p->PRpart = b + oPRp;
     p->PLpart = b + oPLp;
+    p->prpart_bytes = oPLp - oPRp;
+    p->plpart_bytes = oG - oPLp;
     p->Gtmp = b + oG;
     p->grams = (double*)(b + oGr);
     p->scal = (double*)(b + oS);
@@ -512,10 +518,13 @@ static int run_side(cpgrad_plan_s* p, const FacSet<TC>& fs, int side, void* cons
     // first mode of the side on the multi-block kernels
     const int n = n_first;
     void* g = update ? p->Gtmp : G[n - 1];
+    // the side's split partials are summed by now: their buffer holds the gradient's parts
     if (side == 0)
-        CPG_TRY(launch_grad(p->fdt, Z, p->ld, g, &fs, p->Jn[n - 1], p->dims[n - 1], 1, 0, n - 1, 0, 0, p->stream));
+        CPG_TRY(launch_grad_split(p->fdt, Z, p->ld, g, &fs, p->Jn[n - 1], p->dims[n - 1], 1, 0, n - 1, 0, 0,
+                                  p->PRpart, p->prpart_bytes, p->stream));
     else
-        CPG_TRY(launch_grad(p->fdt, Z, p->ld, g, &fs, 1, p->dims[n - 1], p->Kn[n], 0, 0, n, N - n, p->stream));
+        CPG_TRY(launch_grad_split(p->fdt, Z, p->ld, g, &fs, 1, p->dims[n - 1], p->Kn[n], 0, 0, n, N - n, p->PLpart,
+                                  p->plpart_bytes, p->stream));
     if (update || init) {
         EpiArgs<TC> b = a;
         b.n_first = n;
@@ -605,12 +614,13 @@ static int run_both_sides(cpgrad_plan_s* p, const FacSet<TC>& fs, void* const* A
             a[na++] = e;
             continue;
         }
+        // the side's split partials are summed by now: their buffer holds the gradient's parts
         if (s == 0)
-            CPG_TRY(launch_grad(p->fdt, Z, p->ld, G[n - 1], &fs, p->Jn[n - 1], p->dims[n - 1], 1, 0, n - 1, 0, 0,
-                                p->stream));
+            CPG_TRY(launch_grad_split(p->fdt, Z, p->ld, G[n - 1], &fs, p->Jn[n - 1], p->dims[n - 1], 1, 0, n - 1, 0,
+                                      0, p->PRpart, p->prpart_bytes, p->stream));
         else
-            CPG_TRY(launch_grad(p->fdt, Z, p->ld, G[n - 1], &fs, 1, p->dims[n - 1], p->Kn[n], 0, 0, n, N - n,
-                                p->stream));
+            CPG_TRY(launch_grad_split(p->fdt, Z, p->ld, G[n - 1], &fs, 1, p->dims[n - 1], p->Kn[n], 0, 0, n, N - n,
+                                      p->PLpart, p->plpart_bytes, p->stream));
         if (n_count == 1) continue;
         const int nn = s == 0 ? n - 1 : n + 1;
         if (s == 0)

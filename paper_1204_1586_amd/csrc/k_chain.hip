@@ -7,6 +7,8 @@
 // All reductions run in a fixed order, so results are bitwise reproducible.
 #include "cpg_device.h"
 
+#include <algorithm>
+
 namespace cpg {
 
 struct d4s {
@@ -542,10 +544,15 @@ __device__ __forceinline__ void kr_weights4(const FacSet<TC>& fs, int first, int
     }
 }
 
-template <typename TC>
+// SPLIT: block (i, s) of a (I, S) grid takes terms [s chunk, (s + 1) chunk) and
+// writes its float64 sums to part[(i S + s) R + r]; k_grad_sum adds the S
+// parts of each entry in order.  (Used when a row has many terms and there
+// are few rows: the split fills the chip.)
+template <typename TC, bool SPLIT>
 __global__ __launch_bounds__(kGradMaxThreads) void k_grad(const TC* __restrict__ Z, int ld, TC* __restrict__ G,
                                                           FacSet<TC> fs, int64_t lo_n, int64_t I, int64_t hi_n,
-                                                          int lo_first, int lo_count, int hi_first, int hi_count) {
+                                                          int lo_first, int lo_count, int hi_first, int hi_count,
+                                                          double* __restrict__ part, int64_t chunk) {
     __shared__ double spart[(kGradMaxThreads / 64) * 16 * 4];
     const int R = fs.R;
     const int tid = threadIdx.x;
@@ -556,11 +563,13 @@ __global__ __launch_bounds__(kGradMaxThreads) void k_grad(const TC* __restrict__
     const int nslots = (int)blockDim.x / nqp;
     const int slot = tid / nqp;
     const int64_t i = blockIdx.x;
-    const int64_t T = lo_n * hi_n;
+    const int64_t Tall = lo_n * hi_n;
+    const int64_t tb = SPLIT ? (int64_t)blockIdx.y * chunk : 0;
+    const int64_t T = SPLIT ? min(Tall, tb + chunk) : Tall;
     constexpr int kGradBatch = grad_batch<TC>();
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    if (q < nq) {
-        for (int64_t t0 = slot; t0 < T; t0 += (int64_t)kGradBatch * nslots) {
+    if (q < nq && tb < T) {
+        for (int64_t t0 = tb + slot; t0 < T; t0 += (int64_t)kGradBatch * nslots) {
             double z[kGradBatch][4];
             int64_t lo[kGradBatch], hi[kGradBatch];
 #pragma unroll
@@ -595,24 +604,76 @@ __global__ __launch_bounds__(kGradMaxThreads) void k_grad(const TC* __restrict__
 #pragma unroll
             for (int c = 0; c < 4; ++c) v[c] += spart[(ww * 16 + tid) * 4 + c];
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-            if (4 * tid + c < R) G[i * R + 4 * tid + c] = (TC)v[c];
+        for (int c = 0; c < 4; ++c) {
+            if (4 * tid + c >= R) continue;
+            if constexpr (SPLIT)
+                part[(i * gridDim.y + blockIdx.y) * R + 4 * tid + c] = v[c];
+            else
+                G[i * R + 4 * tid + c] = (TC)v[c];
+        }
     }
+}
+
+template <typename TC>
+__global__ __launch_bounds__(256) void k_grad_sum(const double* __restrict__ part, int64_t I, int R, int S,
+                                                  TC* __restrict__ G) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= I * R) return;
+    const int64_t i = e / R;
+    const int r = (int)(e - i * R);
+    double v = 0.0;
+    for (int s = 0; s < S; ++s) v += part[(i * S + s) * R + r];
+    G[e] = (TC)v;
+}
+
+template <typename TC>
+static hipError_t grad_dispatch(const void* Z, int ld, void* G, const void* facset, int64_t lo_n, int64_t I,
+                                int64_t hi_n, int lo_first, int lo_count, int hi_first, int hi_count, int S,
+                                double* part, hipStream_t s) {
+    const FacSet<TC>& fs = *(const FacSet<TC>*)facset;
+    const int64_t T = lo_n * hi_n;
+    const int64_t loads = T * (ld >> 2) / S;
+    // a wide block when a block's rows have many terms
+    const dim3 block(loads >= 16 * kGradMaxThreads ? kGradMaxThreads : 256);
+    if (S <= 1) {
+        hipLaunchKernelGGL((k_grad<TC, false>), dim3((unsigned)I), block, 0, s, (const TC*)Z, ld, (TC*)G, fs, lo_n, I,
+                           hi_n, lo_first, lo_count, hi_first, hi_count, nullptr, (int64_t)0);
+    } else {
+        const int64_t chunk = (T + S - 1) / S;
+        hipLaunchKernelGGL((k_grad<TC, true>), dim3((unsigned)I, (unsigned)S), block, 0, s, (const TC*)Z, ld, (TC*)G,
+                           fs, lo_n, I, hi_n, lo_first, lo_count, hi_first, hi_count, part, chunk);
+        hipLaunchKernelGGL(k_grad_sum<TC>, dim3((unsigned)((I * fs.R + 255) / 256)), dim3(256), 0, s, part, I,
+                           fs.R, S, (TC*)G);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_grad(int fdt, const void* Z, int ld, void* G, const void* facset, int64_t lo_n, int64_t I,
                        int64_t hi_n, int lo_first, int lo_count, int hi_first, int hi_count, hipStream_t s) {
     if ((ld & 3) != 0 || ld > 64 || I < 1) return hipErrorInvalidValue;
-    // a wide block when the row has many terms
-    const int64_t loads = lo_n * hi_n * (ld >> 2);
-    const dim3 block(loads >= 16 * kGradMaxThreads ? kGradMaxThreads : 256);
     if (fdt == CPG_F64)
-        hipLaunchKernelGGL(k_grad<double>, dim3((unsigned)I), block, 0, s, (const double*)Z, ld, (double*)G,
-                           *(const FacSet<double>*)facset, lo_n, I, hi_n, lo_first, lo_count, hi_first, hi_count);
-    else
-        hipLaunchKernelGGL(k_grad<float>, dim3((unsigned)I), block, 0, s, (const float*)Z, ld, (float*)G,
-                           *(const FacSet<float>*)facset, lo_n, I, hi_n, lo_first, lo_count, hi_first, hi_count);
-    return hipGetLastError();
+        return grad_dispatch<double>(Z, ld, G, facset, lo_n, I, hi_n, lo_first, lo_count, hi_first, hi_count, 1,
+                                     nullptr, s);
+    return grad_dispatch<float>(Z, ld, G, facset, lo_n, I, hi_n, lo_first, lo_count, hi_first, hi_count, 1, nullptr,
+                                s);
+}
+
+// launch_grad with the terms of each row split over up to 16 blocks when the
+// rows are few and long (I S >= 512 blocks, at least 64 terms a block), the
+// float64 parts in `scratch` (bytes given; fewer splits when it is short).
+hipError_t launch_grad_split(int fdt, const void* Z, int ld, void* G, const void* facset, int64_t lo_n, int64_t I,
+                             int64_t hi_n, int lo_first, int lo_count, int hi_first, int hi_count, void* scratch,
+                             size_t scratch_bytes, hipStream_t s) {
+    if ((ld & 3) != 0 || ld > 64 || I < 1) return hipErrorInvalidValue;
+    const int R = ((const FacSet<float>*)facset)->R;   // N, R lead both factor-set layouts
+    const int64_t T = lo_n * hi_n;
+    int S = (int)std::min<int64_t>(16, (512 + I - 1) / I);
+    while (S > 1 && (T / S < 64 || (size_t)(I * S * R) * sizeof(double) > scratch_bytes)) --S;
+    if (fdt == CPG_F64)
+        return grad_dispatch<double>(Z, ld, G, facset, lo_n, I, hi_n, lo_first, lo_count, hi_first, hi_count, S,
+                                     (double*)scratch, s);
+    return grad_dispatch<float>(Z, ld, G, facset, lo_n, I, hi_n, lo_first, lo_count, hi_first, hi_count, S,
+                                (double*)scratch, s);
 }
 
 // ---------------------------------------------------------------------------
