@@ -265,10 +265,63 @@ __global__ __launch_bounds__(256) void k_contract_mfma_f32(const float* __restri
             fb += nch * 64;
         }
     };
-    auto gen_lds = [&](v4f (&t)[kKrBatch], int base, bool with_left) {
-        uint32_t idxL[16], idxR[kKrBatch];
-        int r4[kKrBatch];
-        if (DO_L && with_left) {
+    // One Khatri-Rao row from the staged factors, formed by one thread: its
+    // index unravels into the indices of modes m0 .. m1-1 with one division per
+    // mode, and the RT products (float32, mode order) read whole factor rows
+    // from LDS.  Ranks past R and a row index past `lim` give zeros.
+    auto kr_row_lds = [&](float (&v)[RT], int64_t row, int64_t lim, int m0, int m1) {
+        const bool ok = row < lim;
+#pragma unroll
+        for (int r = 0; r < RT; ++r) v[r] = ok && r < R ? 1.f : 0.f;
+        uint32_t idx = ok ? (uint32_t)row : 0u;
+        int fb = 0;
+        for (int m = 0; m < m0; ++m) fb += (((int)kg.fd[m].d * R + 63) >> 6) << 6;
+        for (int m = m0; m < m1; ++m) {
+            const FastDiv f = kg.fd[m];
+            const uint32_t qd = fast_div(idx, f);
+            const float* Fr = sFac + fb + (int)(idx - qd * f.d) * R;
+            idx = qd;
+            if (R >= RT) {
+#pragma unroll
+                for (int r = 0; r < RT; ++r) v[r] *= Fr[r];
+            } else {
+#pragma unroll
+                for (int r = 0; r < RT; ++r) v[r] *= r < R ? Fr[min(r, R - 1)] : 0.f;
+            }
+            fb += (((int)f.d * R + 63) >> 6) << 6;
+        }
+    };
+    // KR_R rows of the block's steps: one row per thread and pass
+    auto krr_rows = [&]() {
+        const int nrow = (int)(nsteps * kStep);
+        for (int kk = tid; kk < nrow; kk += 256) {
+            float v[RT];
+            kr_row_lds(v, step_col(kk / kStep) + (kk & (kStep - 1)), K, kg.nstar, kg.N);
+#pragma unroll
+            for (int g = 0; g < RT / 4; ++g)
+                *(v4f*)(sKRR + kk * KRLD + 4 * g) = v4f{v[4 * g], v[4 * g + 1], v[4 * g + 2], v[4 * g + 3]};
+        }
+    };
+    // KR_L rows of this wave.  Up to 32 ranks: lane l forms row jw + l into the
+    // wave's transpose area (free until the first step), and every lane then
+    // reads its MFMA operand from there.  Wider tiles: each lane forms its own
+    // operand entries, one division per row, mode and entry.
+    auto krl_rows = [&]() {
+        if constexpr (DO_L && NRT <= 2) {
+            constexpr int LD = RT + 1;   // odd stride: the operand reads hit distinct banks
+            static_assert(64 * LD <= kStep * kTLd, "a wave's Khatri-Rao rows fit its transpose area");
+            float* sK = sT[w];
+            float v[RT];
+            kr_row_lds(v, jw + l, J, 0, kg.nstar);
+#pragma unroll
+            for (int r = 0; r < RT; ++r) sK[l * LD + r] = v[r];
+            lds_wave_sync();
+#pragma unroll
+            for (int s = 0; s < 16; ++s)
+#pragma unroll
+                for (int rt = 0; rt < NRT; ++rt) krl[rt][s] = sK[(16 * q + s) * LD + rt * 16 + c16];
+        } else if constexpr (DO_L) {
+            uint32_t idxL[16];
 #pragma unroll
             for (int s = 0; s < 16; ++s) {
                 const int64_t j = jw + 16 * q + s;
@@ -276,25 +329,10 @@ __global__ __launch_bounds__(256) void k_contract_mfma_f32(const float* __restri
 #pragma unroll
                 for (int rt = 0; rt < NRT; ++rt) krl[rt][s] = j < J ? 1.f : 0.f;
             }
-        }
-        if (DO_R) {
-#pragma unroll
-            for (int u = 0; u < kKrBatch; ++u) {
-                const int e = base + u * 256 + tid;
-                const int kk = e / (RT / 4);
-                r4[u] = (e - kk * (RT / 4)) * 4;
-                const int64_t k = step_col(kk / kStep) + (kk & (kStep - 1));
-                const bool ok = e < n4 && k < K;
-                idxR[u] = ok ? (uint32_t)k : 0u;
-                const float one = ok ? 1.f : 0.f;
-                t[u] = v4f{one, one, one, one};
-            }
-        }
-        int fb = 0;
-        for (int m = 0; m < kg.N; ++m) {
-            const FastDiv f = kg.fd[m];
-            const float* Fm = sFac + fb;
-            if (DO_L && with_left && m < kg.nstar) {
+            int fb = 0;
+            for (int m = 0; m < kg.nstar; ++m) {
+                const FastDiv f = kg.fd[m];
+                const float* Fm = sFac + fb;
 #pragma unroll
                 for (int s = 0; s < 16; ++s) {
                     const uint32_t qd = fast_div(idxL[s], f);
@@ -307,22 +345,8 @@ __global__ __launch_bounds__(256) void k_contract_mfma_f32(const float* __restri
                         krl[rt][s] *= r < R ? x : 0.f;
                     }
                 }
+                fb += (((int)f.d * R + 63) >> 6) << 6;
             }
-            if (DO_R && m >= kg.nstar) {
-#pragma unroll
-                for (int u = 0; u < kKrBatch; ++u) {
-                    const uint32_t qd = fast_div(idxR[u], f);
-                    const uint32_t i = idxR[u] - qd * f.d;
-                    idxR[u] = qd;
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        const int r = r4[u] + c;
-                        const float x = Fm[i * R + min(r, R - 1)];
-                        t[u][c] *= r < R ? x : 0.f;
-                    }
-                }
-            }
-            fb += (((int)f.d * R + 63) >> 6) << 6;
         }
     };
 
@@ -450,11 +474,8 @@ __global__ __launch_bounds__(256) void k_contract_mfma_f32(const float* __restri
 #pragma unroll
         for (int d = 0; d < kDepth; ++d) load_step(buf[d], d);
         CPG_CONTRACT_MARK(41);
-        v4f krt[kKrBatch];
-        for (int base = 0; base == 0 || (DO_R && base < n4); base += kKrBatch * 256) {
-            gen_lds(krt, base, base == 0);
-            if (DO_R) store_krr(krt, base);
-        }
+        krl_rows();
+        if (DO_R) krr_rows();
         CPG_CONTRACT_MARK(42);
     } else {
         v4f krt[kKrBatch];
