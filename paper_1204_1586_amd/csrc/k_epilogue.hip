@@ -499,6 +499,11 @@ __device__ __forceinline__ bool wave_eliminate(int R, int64_t I, const double* s
                 const double piv = readlane_d(gc[k], k);
                 ok = ok && piv > 0.0 && isfinite(piv);
                 double rp = __builtin_amdgcn_rcp(piv);
+                // pinned here for 17-20 register columns: the compiler otherwise
+                // emits the estimate after the multipliers, on the step's critical
+                // path (measured faster there; no gain with fewer columns, and
+                // spills with 32)
+                if constexpr (RE > 16 && RE <= 20) asm volatile("" : "+v"(rp));
                 __builtin_amdgcn_sched_barrier(0);
                 double mk[RE];
 #pragma unroll
