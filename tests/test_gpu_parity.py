@@ -46,6 +46,7 @@ CASES = [
     ((12, 10, 8, 6, 4), 32, "bf16"),
     ((36, 20, 28, 33), 48, "f32"),
     ((8, 600, 7), 64, "f32"),
+    ((12, 20, 16, 24), 64, "f32"),          # rank tile 64 with every factor staged in LDS
     ((12, 40, 36, 10), 20, "f32"),
     ((6, 5, 4, 6, 5, 4, 6), 10, "f32"),       # 7-D, J_{n*} = 120: float32 matrix cores, three-mode chains
     ((4, 3, 5, 4, 3, 2, 6), 10, "f32"),       # 7-D, J_{n*} = 60
