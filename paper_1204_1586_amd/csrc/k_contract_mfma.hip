@@ -281,45 +281,114 @@ __global__ __launch_bounds__(256) void k_contract_mfma_f32(const float* __restri
             const uint32_t qd = fast_div(idx, f);
             const float* Fr = sFac + fb + (int)(idx - qd * f.d) * R;
             idx = qd;
-            if (R >= RT) {
+            // all RT entries read (past R: the next row, or the slack after
+            // the staged factors), those past R replaced by zero
 #pragma unroll
-                for (int r = 0; r < RT; ++r) v[r] *= Fr[r];
-            } else {
-#pragma unroll
-                for (int r = 0; r < RT; ++r) v[r] *= r < R ? Fr[min(r, R - 1)] : 0.f;
+            for (int r = 0; r < RT; ++r) {
+                const float x = Fr[r];
+                v[r] *= r < R ? x : 0.f;
             }
             fb += (((int)f.d * R + 63) >> 6) << 6;
         }
     };
-    // KR_R rows of the block's steps: one row per thread and pass
-    auto krr_rows = [&]() {
-        const int nrow = (int)(nsteps * kStep);
-        for (int kk = tid; kk < nrow; kk += 256) {
-            float v[RT];
-            kr_row_lds(v, step_col(kk / kStep) + (kk & (kStep - 1)), K, kg.nstar, kg.N);
+    // A KR_L row and a KR_R row formed together: round j reads mode j of the
+    // left product and mode n*+j of the right one before multiplying either,
+    // so the LDS round trips of the two rows overlap (both divisors are read
+    // before either row's LDS reads, whose wait would otherwise include them).
+    // The products are those of kr_row_lds, in the same order.
+    auto rows_paired = [&](float (&vl)[RT], int64_t rowL, float (&vr)[RT], int64_t rowR, bool doL) {
+        const bool okL = rowL < J, okR = rowR < K;
 #pragma unroll
-            for (int g = 0; g < RT / 4; ++g)
-                *(v4f*)(sKRR + kk * KRLD + 4 * g) = v4f{v[4 * g], v[4 * g + 1], v[4 * g + 2], v[4 * g + 3]};
+        for (int r = 0; r < RT; ++r) {
+            vl[r] = okL && r < R ? 1.f : 0.f;
+            vr[r] = okR && r < R ? 1.f : 0.f;
+        }
+        uint32_t iL = okL ? (uint32_t)rowL : 0u, iR = okR ? (uint32_t)rowR : 0u;
+        int fbL = 0, fbR = 0;
+        for (int m = 0; m < kg.nstar; ++m) fbR += (((int)kg.fd[m].d * R + 63) >> 6) << 6;
+        const int nL = doL ? kg.nstar : 0, nR = kg.N - kg.nstar;
+        const int rounds = nL > nR ? nL : nR;
+        // one path for every R (a branch here makes the compiler wait for all
+        // LDS reads where the paths join): all RT entries, past R zero
+        auto read_row = [&](float (&x)[RT], const float* Fr) {
+#pragma unroll
+            for (int r = 0; r < RT; ++r) {
+                const float y = Fr[r];
+                x[r] = r < R ? y : 0.f;
+            }
+        };
+        for (int j = 0; j < rounds; ++j) {
+            const bool aL = j < nL, aR = j < nR;
+            const FastDiv fL = kg.fd[aL ? j : 0], fR = kg.fd[kg.nstar + (aR ? j : 0)];
+            const uint32_t qL = fast_div(iL, fL), qR = fast_div(iR, fR);
+            int oL = fbL + (int)(iL - qL * fL.d) * R, oR = fbR + (int)(iR - qR * fR.d) * R;
+            // both offsets formed here, before the first LDS read of the round
+            asm volatile("" : "+v"(oL), "+v"(oR));
+            float xl[RT], xr[RT];
+            if (aL) {
+                read_row(xl, sFac + oL);
+                iL = qL;
+            }
+            if (aR) {
+                read_row(xr, sFac + oR);
+                iR = qR;
+            }
+            if (aL) {
+#pragma unroll
+                for (int r = 0; r < RT; ++r) vl[r] *= xl[r];
+                fbL += (((int)fL.d * R + 63) >> 6) << 6;
+            }
+            if (aR) {
+#pragma unroll
+                for (int r = 0; r < RT; ++r) vr[r] *= xr[r];
+                fbR += (((int)fR.d * R + 63) >> 6) << 6;
+            }
         }
     };
-    // KR_L rows of this wave.  Up to 32 ranks: lane l forms row jw + l into the
-    // wave's transpose area (free until the first step), and every lane then
-    // reads its MFMA operand from there.  Wider tiles: each lane forms its own
-    // operand entries, one division per row, mode and entry.
-    auto krl_rows = [&]() {
-        if constexpr (DO_L && NRT <= 2) {
-            constexpr int LD = RT + 1;   // odd stride: the operand reads hit distinct banks
-            static_assert(64 * LD <= kStep * kTLd, "a wave's Khatri-Rao rows fit its transpose area");
-            float* sK = sT[w];
+    auto store_krr_row = [&](const float (&v)[RT], int kk) {
+#pragma unroll
+        for (int g = 0; g < RT / 4; ++g)
+            *(v4f*)(sKRR + kk * KRLD + 4 * g) = v4f{v[4 * g], v[4 * g + 1], v[4 * g + 2], v[4 * g + 3]};
+    };
+    // The block's Khatri-Rao rows from the staged factors, one row per thread
+    // and pass: KR_R rows of the block's steps into LDS; up to 32 ranks, lane l
+    // also forms its wave's KR_L row jw + l (paired with its first KR_R row)
+    // into the wave's transpose area (free until the first step), and every
+    // lane then reads its MFMA operand from there.  Wider tiles: each lane
+    // forms its own KR_L operand entries, one division per row, mode and entry.
+    auto form_rows = [&]() {
+        constexpr bool kLRow = DO_L && NRT <= 2;
+        constexpr int LD = RT + 1;   // odd stride: the operand reads hit distinct banks
+        static_assert(!kLRow || 64 * LD <= kStep * kTLd, "a wave's Khatri-Rao rows fit its transpose area");
+        const int nrow = DO_R ? (int)(nsteps * kStep) : 0;
+        int kk = tid;
+        if constexpr (DO_R) {
+            float vl[RT], vr[RT];
+            rows_paired(vl, kLRow ? jw + l : J, vr, kk < nrow ? step_col(kk / kStep) + (kk & (kStep - 1)) : K,
+                        kLRow);
+            if (kk < nrow) store_krr_row(vr, kk);
+            if constexpr (kLRow) {
+#pragma unroll
+                for (int r = 0; r < RT; ++r) sT[w][l * LD + r] = vl[r];
+            }
+            kk += 256;
+        } else if constexpr (kLRow) {
             float v[RT];
             kr_row_lds(v, jw + l, J, 0, kg.nstar);
 #pragma unroll
-            for (int r = 0; r < RT; ++r) sK[l * LD + r] = v[r];
+            for (int r = 0; r < RT; ++r) sT[w][l * LD + r] = v[r];
+        }
+        for (; kk < nrow; kk += 256) {
+            float v[RT];
+            kr_row_lds(v, step_col(kk / kStep) + (kk & (kStep - 1)), K, kg.nstar, kg.N);
+            store_krr_row(v, kk);
+        }
+        if constexpr (kLRow) {
             lds_wave_sync();
 #pragma unroll
             for (int s = 0; s < 16; ++s)
 #pragma unroll
-                for (int rt = 0; rt < NRT; ++rt) krl[rt][s] = sK[(16 * q + s) * LD + rt * 16 + c16];
+                for (int rt = 0; rt < NRT; ++rt) krl[rt][s] = sT[w][(16 * q + s) * LD + rt * 16 + c16];
         } else if constexpr (DO_L) {
             uint32_t idxL[16];
 #pragma unroll
@@ -474,8 +543,7 @@ __global__ __launch_bounds__(256) void k_contract_mfma_f32(const float* __restri
 #pragma unroll
         for (int d = 0; d < kDepth; ++d) load_step(buf[d], d);
         CPG_CONTRACT_MARK(41);
-        krl_rows();
-        if (DO_R) krr_rows();
+        form_rows();
         CPG_CONTRACT_MARK(42);
     } else {
         v4f krt[kKrBatch];
@@ -532,7 +600,9 @@ constexpr int64_t kLdsPerCu = 160 * 1024;
 int64_t mfma_f32_max_cols(int rt, int roles, int64_t fac_stage) {
     const int nrt = rt / 16;
     const int64_t row = (int64_t)(rt + 4) * 4;
-    const int64_t st = static_lds(nrt, (roles & 2) != 0) + fac_stage * 4;
+    // staged factors plus one rank tile of slack after them (rows are read
+    // whole, up to RT floats past a factor's last row)
+    const int64_t st = static_lds(nrt, (roles & 2) != 0) + (fac_stage > 0 ? (fac_stage + rt) * 4 : 0);
     // one block per CU (the tiling targets one long-running block per CU)
     const int64_t budget = kLdsPerCu - st;
     return std::max<int64_t>(kStep, (budget / row) / kStep * kStep);
@@ -542,7 +612,8 @@ template <int NRT, bool DO_R, bool DO_L>
 static hipError_t launch_one(dim3 grid, const float* Y, int64_t J, int64_t K, int64_t kcols, const MfmaBufs& o,
                              hipStream_t s) {
     auto kern = k_contract_mfma_f32<NRT, DO_R, DO_L>;
-    const size_t dyn = (DO_R ? (size_t)kcols * (NRT * 16 + 4) * sizeof(float) : 0) + (size_t)o.fac_stage * 4;
+    const size_t dyn = (DO_R ? (size_t)kcols * (NRT * 16 + 4) * sizeof(float) : 0) +
+                       (o.fac_stage > 0 ? (size_t)(o.fac_stage + NRT * 16) * 4 : 0);
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
